@@ -1,0 +1,132 @@
+/*
+ * CPU oracle for the Jacobi-style stencil sweep.  TEST INFRASTRUCTURE ONLY:
+ * it is used by the test-suite, by the smoke check and by the CPU-baseline leg
+ * of the benchmark, never by the GPU library.  It shares no code, header or
+ * table with the GPU path.
+ *
+ * What it computes (AN5D, Background "Stencil Computation"; Fig. 4 and the
+ * host-code description in "Code Generation"; Table 3 for the star/box
+ * synthetic stencils):
+ *
+ *   A is a double-buffered, padded grid A[2][P0][P1] (2D) or A[2][P0][P1][P2]
+ *   (3D), P_i = I_i + 2*radius.  The border of width `radius` on every face is
+ *   the fixed boundary: it is read but never written.  For t = 0..T-1 every
+ *   interior cell p of A[(t+1)%2] receives
+ *
+ *       A[(t+1)%2][p] = sum_k c_k * A[t%2][p + o_k]
+ *
+ *   and the result of the whole sweep is A[T%2].
+ *
+ * The offsets o_k are enumerated in ONE canonical order: lexicographic in
+ * (d0, d1[, d2]), each component in [-radius, radius], axis 0 (the outermost,
+ * slowest-varying axis) first.  A box stencil keeps every offset; a star
+ * stencil keeps the offsets with at most one non-zero component.  For the 2D
+ * 5-point star this order is exactly the term order printed in Fig. 4.
+ *
+ * Arithmetic: the sum is formed left to right in that order in the working
+ * precision, product then add, with no fused multiply-add (this file must be
+ * built with -ffp-contract=off and without fast-math).  Cells are
+ * independent, so the OpenMP split over axis 0 gives the same bits as a
+ * serial run.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_MAX_POINTS 729 /* (2*4+1)^3: box, radius 4, 3D */
+
+/* Canonical offsets; returns their count, or -1 for an unsupported stencil.
+ * out[3*k + a] is component a of offset k (unused components are 0). */
+int oracle_offsets(int ndim, int radius, int box, int32_t *out)
+{
+    if ((ndim != 2 && ndim != 3) || radius < 1 || radius > 4)
+        return -1;
+    int n = 0;
+    int r = radius;
+    int lo2 = (ndim == 3) ? -r : 0, hi2 = (ndim == 3) ? r : 0;
+    for (int d0 = -r; d0 <= r; ++d0)
+        for (int d1 = -r; d1 <= r; ++d1)
+            for (int d2 = lo2; d2 <= hi2; ++d2) {
+                int nonzero = (d0 != 0) + (d1 != 0) + (d2 != 0);
+                if (!box && nonzero > 1)
+                    continue;
+                if (out) {
+                    out[3 * n + 0] = d0;
+                    out[3 * n + 1] = d1;
+                    out[3 * n + 2] = d2;
+                }
+                ++n;
+            }
+    return n;
+}
+
+/* One definition of the sweep per working precision.  `buf0` holds the
+ * initial padded grid (boundary included); `buf1` receives a copy of it so
+ * both buffers carry the same boundary; on return the result is in
+ * buf[T % 2].  Returns T % 2, or a negative value on bad arguments. */
+#define ORACLE_SWEEP(NAME, REAL)                                                  \
+    int NAME(int ndim, int radius, int box, const int64_t *interior,              \
+             int64_t steps, const REAL *coeffs, int64_t n_coeffs,                 \
+             REAL *buf0, REAL *buf1, int threads)                                 \
+    {                                                                             \
+        int32_t off3[3 * ORACLE_MAX_POINTS];                                      \
+        int n = oracle_offsets(ndim, radius, box, off3);                          \
+        if (n < 0 || n != n_coeffs || steps < 0 || !buf0 || !buf1 || !coeffs)     \
+            return -1;                                                            \
+        int64_t I0 = interior[0], I1 = interior[1];                               \
+        int64_t I2 = (ndim == 3) ? interior[2] : 1;                               \
+        if (I0 < 1 || I1 < 1 || I2 < 1)                                           \
+            return -1;                                                            \
+        int64_t r = radius;                                                       \
+        int64_t P0 = I0 + 2 * r, P1 = I1 + 2 * r;                                 \
+        int64_t P2 = (ndim == 3) ? I2 + 2 * r : 1;                                \
+        int64_t r2 = (ndim == 3) ? r : 0;                                         \
+        int64_t total = P0 * P1 * P2;                                             \
+        int64_t lin[ORACLE_MAX_POINTS];                                           \
+        for (int k = 0; k < n; ++k)                                               \
+            lin[k] = (int64_t)off3[3 * k] * P1 * P2 +                             \
+                     (int64_t)off3[3 * k + 1] * P2 + (int64_t)off3[3 * k + 2];    \
+        memcpy(buf1, buf0, (size_t)total * sizeof(REAL));                         \
+        if (threads > 0) {                                                        \
+            OMP_SET(threads);                                                     \
+        }                                                                         \
+        for (int64_t t = 0; t < steps; ++t) {                                     \
+            const REAL *src = (t % 2 == 0) ? buf0 : buf1;                         \
+            REAL *dst = (t % 2 == 0) ? buf1 : buf0;                               \
+            OMP_FOR                                                               \
+            for (int64_t i0 = r; i0 < r + I0; ++i0)                               \
+                for (int64_t i1 = r; i1 < r + I1; ++i1)                           \
+                    for (int64_t i2 = r2; i2 < r2 + I2; ++i2) {                   \
+                        int64_t p = (i0 * P1 + i1) * P2 + i2;                     \
+                        REAL acc = coeffs[0] * src[p + lin[0]];                   \
+                        for (int k = 1; k < n; ++k)                               \
+                            acc = acc + coeffs[k] * src[p + lin[k]];              \
+                        dst[p] = acc;                                             \
+                    }                                                             \
+        }                                                                         \
+        return (int)(steps % 2);                                                  \
+    }
+
+#ifdef _OPENMP
+#define OMP_SET(n) omp_set_num_threads(n)
+#define OMP_FOR _Pragma("omp parallel for schedule(static)")
+#else
+#define OMP_SET(n) ((void)(n))
+#define OMP_FOR
+#endif
+
+ORACLE_SWEEP(oracle_sweep_f64, double)
+ORACLE_SWEEP(oracle_sweep_f32, float)
+
+/* Number of OpenMP threads a parallel region would use (1 without OpenMP). */
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
