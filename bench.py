@@ -1,0 +1,310 @@
+#!/usr/bin/env python3
+"""Benchmark of the temporally blocked stencil sweep on one MI355X.
+
+Workload (one "step" = one whole sweep): 2D 5-point star (radius 1), float32,
+16384 x 16384 interior plus a 1-cell fixed boundary, 1000 time steps, random
+coefficients normalised to sum 1 and a U[0,1) grid from seed 1473+1, with the
+library's tuned temporal blocking degree b_T.  Inputs are resident in HBM
+before the timed region; timing uses HIP events on the stream the kernels run
+on.  Reported:
+
+* value: effective GCell-updates/s = interior cells * T / seconds (redundant
+  halo work is not credited) and its fraction of the b_T = 1 HBM bound;
+* roofline: the dominant kernel (one b_T round) timed per launch, against the
+  HBM roofline (algorithmic bytes 2*w per cell per launch) and the vector-ALU
+  roofline (algorithmic FLOP (2n-1)*b_T per cell per launch), whichever the
+  kernel is closer to; HBM traffic from rocprofv3 counters when the counter
+  record matches the current kernel source;
+* sweep: the other stencils and dtypes of the same workload family (star
+  r = 1..4, box r = 1..2, float32 and float64, T = 1000) at their tuned b_T,
+  and the b_T = 1..10 curve of the 5-point star;
+* cpu_baseline: the CPU oracle (naive loop, OpenMP) on a bounded sample of the
+  same grid.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep]
+       python bench.py --probe      (a few launches of the dominant kernel and a
+                                     copy of known size, for rocprofv3 counters)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import stencil_inputs as si  # noqa: E402
+
+N = 16384
+T_STEPS = 1000
+HBM_PEAK_GBS = 8000.0
+# Vector FMA issue ceiling: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP x 2.4 GHz.
+# Packed float32 math is disabled in this build, so float32 and float64 share it.
+ALU_PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
+ALU_PEAK_PUBLISHED = {"f32": 157.3, "f64": 78.6}
+STENCILS = [(1, False), (2, False), (3, False), (4, False), (1, True), (2, True)]
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_sweep2d_star_r1_f32_16384.json")
+
+
+def npts(r, box):
+    return si.n_points(2, r, box)
+
+
+def flop_per_cell(r, box):
+    return 2 * npts(r, box) - 1  # AN5D Table 3 (FMA counted as 2)
+
+
+def stencil_name(r, box):
+    return "%s2d%dr" % ("box" if box else "star", r)
+
+
+def kernel_source_hash():
+    h = hashlib.sha1()
+    for p in ("paper_2001_01473_amd/csrc/sweep2d.h", "paper_2001_01473_amd/csrc/s5d_internal.h"):
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+class Problem:
+    """Device buffers and a plan for one (stencil, dtype, tuning)."""
+
+    def __init__(self, r, box, dtype, steps=T_STEPS, interior=(N, N), seed=None, **tuning):
+        import torch
+        import paper_2001_01473_amd as s5d
+        self.r, self.box, self.dtype, self.steps = r, box, dtype, steps
+        seed = si.workload_seed(1) if seed is None else seed
+        rng = np.random.default_rng(seed)
+        c = si.random_coeffs(rng, npts(r, box))
+        self.coeffs = c
+        shape = si.padded_shape(interior, r)
+        td = torch.float32 if dtype == "f32" else torch.float64
+        gen = torch.Generator(device="cuda:0").manual_seed(seed)
+        # U[0,1) grid generated on the device (same distribution as the host
+        # generator; the benchmark never compares values)
+        self.buf0 = torch.rand(shape, dtype=td, device="cuda:0", generator=gen)
+        self.buf1 = torch.empty_like(self.buf0)
+        self.init = self.buf0.clone()
+        self.plan = s5d.Plan(ndim=2, radius=r, box=box, dtype=dtype, interior=interior,
+                             steps=steps, coeffs=c, **tuning)
+        self.info = self.plan.query()
+        self.cells = interior[0] * interior[1]
+
+    def reset(self):
+        self.buf0.copy_(self.init)
+
+    def run(self):
+        return self.plan.run(self.buf0, self.buf1)
+
+    def close(self):
+        self.plan.close()
+        del self.buf0, self.buf1, self.init
+
+
+def time_steps(prob, steps, warmup):
+    """Mean seconds per whole sweep over `steps` timed sweeps (HIP events)."""
+    import torch
+    for _ in range(warmup):
+        prob.reset()
+        prob.run()
+    torch.cuda.synchronize()
+    total = 0.0
+    for _ in range(steps):
+        prob.reset()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        prob.run()
+        b.record()
+        b.synchronize()
+        total += a.elapsed_time(b) / 1e3
+    return total / steps
+
+
+def time_one_round(r, box, dtype, bt, launches=20, **tuning):
+    """Average duration of one launch of the b_T kernel (one round), HIP events."""
+    import torch
+    prob = Problem(r, box, dtype, steps=bt, bt=bt, **tuning)
+    for _ in range(3):
+        prob.run()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    # steps = bt: each run is one boundary copy (tiny) plus one sweep launch
+    a.record()
+    for _ in range(launches):
+        prob.run()
+    b.record()
+    b.synchronize()
+    dt = a.elapsed_time(b) / 1e3 / launches
+    info = prob.info
+    prob.close()
+    return dt, info
+
+
+def roofline(r, box, dtype, bt, tuning):
+    w = 4 if dtype == "f32" else 8
+    dt, info = time_one_round(r, box, dtype, bt, **tuning)
+    cells = N * N
+    bytes_alg = 2.0 * w * cells
+    flop_alg = float(flop_per_cell(r, box)) * cells * bt
+    hbm = bytes_alg / dt / 1e9
+    alu = flop_alg / dt / 1e12
+    hbm_frac = hbm / HBM_PEAK_GBS
+    alu_frac = alu / ALU_PEAK_TFLOPS[dtype]
+    traffic = None
+    if os.path.exists(TRAFFIC_RECORD):
+        with open(TRAFFIC_RECORD) as f:
+            rec = json.load(f)
+        if rec.get("kernel_hash") == kernel_source_hash() and rec.get("bt") == bt:
+            traffic = rec.get("hbm_bytes_per_launch")
+    common = {"kernel": "sweep2d %s r=%d %s bt=%d" % ("box" if box else "star", r, dtype, bt),
+              "launch_ms": dt * 1e3, "traffic": traffic,
+              "bytes_per_launch": bytes_alg, "flop_per_launch": flop_alg}
+    if alu_frac >= hbm_frac:
+        out = {"bound": "alu", "achieved": alu, "peak": ALU_PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
+               "frac": alu_frac, "alt": {"bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS,
+                                         "unit": "GB/s", "frac": hbm_frac},
+               "peak_published": ALU_PEAK_PUBLISHED[dtype]}
+    else:
+        out = {"bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": hbm_frac, "alt": {"bound": "alu", "achieved": alu,
+                                         "peak": ALU_PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
+                                         "frac": alu_frac}}
+    out.update(common)
+    return out
+
+
+def cpu_baseline(r, box, dtype, target_s=12.0):
+    """The CPU oracle on a bounded sample: the full grid for a few steps."""
+    import oracle
+    rng = np.random.default_rng(si.workload_seed(1))
+    c = si.random_coeffs(rng, npts(r, box))
+    g = rng.random(si.padded_shape((N, N), r)).astype(np.float32 if dtype == "f32" else np.float64)
+    t0 = time.perf_counter()
+    oracle.sweep(g, radius=r, box=box, coeffs=c, steps=1)
+    one = time.perf_counter() - t0
+    steps = int(max(2, min(40, target_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.sweep(g, radius=r, box=box, coeffs=c, steps=steps)
+    dt = time.perf_counter() - t0
+    return {"value": N * N * steps / dt / 1e9, "unit": "GCell-updates/s",
+            "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": "%s %s %dx%d interior, %d steps (of %d), %.1f s" % (
+                stencil_name(r, box), dtype, N, N, steps, T_STEPS, dt)}
+
+
+def probe(args):
+    """Launches for rocprofv3 counter runs: a copy of known size, then the kernel."""
+    import torch
+    nbytes = 1 << 30
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").uniform_()
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print("probe copy bytes_read=%d bytes_written=%d" % (nbytes, nbytes), flush=True)
+    prob = Problem(1, False, "f32", steps=args.bt, bt=args.bt)
+    for _ in range(args.launches):
+        prob.run()
+    torch.cuda.synchronize()
+    print("probe kernel %s launches=%d" % (json.dumps(prob.info), args.launches), flush=True)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--bt", type=int, default=0, help="force b_T for the headline run")
+    ap.add_argument("--probe", action="store_true")
+    ap.add_argument("--launches", type=int, default=5)
+    args = ap.parse_args(argv)
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the stencil sweep here runs on a single MI355X "
+              "(multi-GPU sharding is described, not built); use --gpus 1", file=sys.stderr)
+        return 2
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    if args.probe:
+        if args.bt == 0:
+            args.bt = 10
+        probe(args)
+        return 0
+
+    tuning = {"bt": args.bt} if args.bt else {}
+    prob = Problem(1, False, "f32", **tuning)
+    info = prob.info
+    sec = time_steps(prob, args.steps, args.warmup)
+    prob.close()
+    gcells = N * N * T_STEPS / sec / 1e9
+    rec = {
+        "metric": "GCell-updates/s & % HBM roofline; batched/served vs plain, p50/p99",
+        "value": gcells, "unit": "GCell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "star2d1r 16384x16384 f32 T=1000", "stencil": "star2d1r",
+                   "interior": [N, N], "time_steps": T_STEPS, "bt": info["bt"],
+                   "tile": info["tile0"], "stream_chunk": info["stream_chunk"],
+                   "cells_per_lane": info["cells_per_lane"]},
+        "pct_hbm_bound": 100.0 * gcells * 2 * 4 / HBM_PEAK_GBS,
+    }
+    print("headline: %.1f GCell/s (%.0f%% of the b_T=1 HBM bound)" %
+          (gcells, rec["pct_hbm_bound"]), file=sys.stderr, flush=True)
+    rec["roofline"] = roofline(1, False, "f32", info["bt"],
+                               {k: info[k] for k in ("stream_chunk", "cells_per_lane")})
+    if not args.no_sweep:
+        sweep = []
+        for dtype in ("f32", "f64"):
+            for r, box in STENCILS:
+                p = Problem(r, box, dtype)
+                s = time_steps(p, 1, 1)
+                w = 4 if dtype == "f32" else 8
+                g = N * N * T_STEPS / s / 1e9
+                sweep.append({"stencil": stencil_name(r, box), "dtype": dtype, "bt": p.info["bt"],
+                              "cells_per_lane": p.info["cells_per_lane"],
+                              "stream_chunk": p.info["stream_chunk"], "gcells": g,
+                              "pct_hbm_bound": 100.0 * g * 2 * w / HBM_PEAK_GBS})
+                p.close()
+                print("sweep %s %s bt=%d: %.1f GCell/s" % (stencil_name(r, box), dtype,
+                                                           sweep[-1]["bt"], g),
+                      file=sys.stderr, flush=True)
+        rec["sweep"] = sweep
+        curve = []
+        for dtype in ("f32", "f64"):
+            for bt in range(1, 11):
+                try:
+                    p = Problem(1, False, dtype, bt=bt)
+                except Exception as e:  # a depth without a compiled kernel
+                    curve.append({"dtype": dtype, "bt": bt, "gcells": None, "note": str(e)[:80]})
+                    continue
+                s = time_steps(p, 1, 1)
+                g = N * N * T_STEPS / s / 1e9
+                curve.append({"dtype": dtype, "bt": bt, "cells_per_lane": p.info["cells_per_lane"],
+                              "stream_chunk": p.info["stream_chunk"], "gcells": g})
+                p.close()
+                print("bt-curve star2d1r %s bt=%d: %.1f GCell/s" % (dtype, bt, g),
+                      file=sys.stderr, flush=True)
+        rec["bt_curve_star2d1r"] = curve
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline(1, False, "f32")
+    torch.cuda.synchronize()
+    print(json.dumps(rec))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,366 @@
+// C ABI of libstencil5d.so: descriptor validation, blocking choice and the
+// round scheduler (AN5D "Host Code": repeated launches of b_T fused steps, the
+// last rounds shortened so the result lands where the modulo double buffer
+// of the C program leaves it).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "s5d_internal.h"
+#include "stencil5d.h"
+
+using s5d::Entry2D;
+using s5d::Kernel2D;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+s5d_status fail(s5d_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+s5d_status device_fail(hipError_t e, const char* what) {
+  return fail(S5D_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Largest radius with kernels, per dimensionality and shape.
+int max_radius(int ndim, int shape) {
+  if (ndim == 2) return shape == S5D_STAR ? 4 : 2;
+  return 0;
+}
+
+const Entry2D* find2d(int dtype, int box, int r, int cpl, int bt) {
+  for (int i = 0; i < s5d::kRegistry2DSize; ++i) {
+    const Entry2D& e = s5d::kRegistry2D[i];
+    if (e.dtype == dtype && e.box == box && e.r == r && e.cpl == cpl && e.bt == bt) return &e;
+  }
+  return nullptr;
+}
+
+int max_bt2d(int dtype, int box, int r, int cpl) {
+  int best = 0;
+  for (int i = 0; i < s5d::kRegistry2DSize; ++i) {
+    const Entry2D& e = s5d::kRegistry2D[i];
+    if (e.dtype == dtype && e.box == box && e.r == r && e.cpl == cpl) best = std::max(best, e.bt);
+  }
+  return best;
+}
+
+// Starting point when the caller leaves b_T to the library: deep blocking for
+// low-order stencils, shallower for high-order and box ones, where the
+// per-level work and the register window grow (AN5D "Scaling Performance").
+int default_bt(int dtype, int box, int r) {
+  static const int f32_star[4] = {10, 8, 6, 5}, f32_box[2] = {8, 4};
+  static const int f64_star[4] = {8, 6, 4, 4}, f64_box[2] = {6, 3};
+  if (dtype == S5D_F32) return box ? f32_box[r - 1] : f32_star[r - 1];
+  return box ? f64_box[r - 1] : f64_star[r - 1];
+}
+
+struct DeviceInfo {
+  int cus = 256;
+  bool ok = false;
+};
+
+DeviceInfo query_device() {
+  DeviceInfo d;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return d;
+  }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
+    d.cus = cus;
+    d.ok = true;
+  } else {
+    (void)hipGetLastError();
+  }
+  return d;
+}
+
+// Stream-block length h_SN from an occupancy model (AN5D "Performance Model",
+// SM efficiency): waves run in rounds of `slots`; a block of h rows costs
+// h + 2*b_T*r steps (warm-up and drain of the fused levels).  Minimise
+// ceil(waves / slots) * (h + 2*b_T*r).
+int choose_chunk(int64_t I0, int64_t ntiles, int64_t slots, int bt, int r) {
+  const int64_t hmin = std::max<int64_t>(16, 4LL * bt * r);
+  int64_t best_h = I0;
+  double best_cost = 1e300;
+  const int64_t max_nch = std::max<int64_t>(1, I0 / hmin);
+  for (int64_t nch = 1; nch <= max_nch && nch <= 65536; ++nch) {
+    const int64_t h = (I0 + nch - 1) / nch;
+    const int64_t nch_eff = (I0 + h - 1) / h;
+    const int64_t waves = ntiles * nch_eff;
+    const int64_t rounds = (waves + slots - 1) / slots;
+    const double cost = static_cast<double>(rounds) * static_cast<double>(h + 2LL * bt * r);
+    if (cost < best_cost * (1.0 - 1e-9)) {
+      best_cost = cost;
+      best_h = h;
+    }
+  }
+  return static_cast<int>(std::min<int64_t>(best_h, INT32_MAX));
+}
+
+// A whole sweep as (n_full rounds of bt) followed by up to three shorter
+// rounds; the total round count has the parity of T, so the result lands in
+// buffer T % 2 (AN5D "Host Code").
+struct RoundSchedule {
+  int64_t n_full = 0;
+  int bt = 1;
+  int tail[3] = {0, 0, 0};
+  int n_tail = 0;
+  int64_t total() const { return n_full + n_tail; }
+};
+
+RoundSchedule schedule_rounds(int64_t T, int bt) {
+  RoundSchedule s;
+  s.bt = bt;
+  if (T <= 0) return s;
+  const int64_t n = (T + bt - 1) / bt;
+  const int last = static_cast<int>(T - (n - 1) * bt);
+  if ((n % 2) == (T % 2)) {
+    if (last == bt) {
+      s.n_full = n;
+    } else {
+      s.n_full = n - 1;
+      s.tail[s.n_tail++] = last;
+    }
+  } else if (last >= 2) {
+    s.n_full = n - 1;
+    s.tail[s.n_tail++] = last - 1;
+    s.tail[s.n_tail++] = 1;
+  } else {
+    // last == 1 and n >= 2 (n == 1 would mean T == 1, which matches parity);
+    // a mismatch needs bt >= 2, so the round before can give up one step.
+    s.n_full = n - 2;
+    s.tail[s.n_tail++] = bt - 1;
+    s.tail[s.n_tail++] = 1;
+    s.tail[s.n_tail++] = 1;
+  }
+  return s;
+}
+
+}  // namespace
+
+struct s5d_plan {
+  s5d_desc d;
+  std::vector<double> coeffs;
+  s5d_tuning tun;
+  int64_t padded[3];
+  int64_t bytes;
+  int elem;
+  Kernel2D by_bt[16];  // index bt: kernel for a round of bt steps (same cells per lane)
+};
+
+extern "C" {
+
+const char* s5d_status_string(s5d_status status) {
+  switch (status) {
+    case S5D_OK: return "S5D_OK";
+    case S5D_EINVAL: return "S5D_EINVAL";
+    case S5D_EUNSUPPORTED: return "S5D_EUNSUPPORTED";
+    case S5D_ENOMEM: return "S5D_ENOMEM";
+    case S5D_EDEVICE: return "S5D_EDEVICE";
+    case S5D_EBUDGET: return "S5D_EBUDGET";
+    default: return "S5D_UNKNOWN";
+  }
+}
+
+const char* s5d_last_error(void) { return g_last_error.c_str(); }
+
+s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_plan** out) {
+  g_last_error.clear();
+  if (!out) return fail(S5D_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!desc) return fail(S5D_EINVAL, "desc is NULL");
+  if (desc->struct_size < sizeof(s5d_desc)) return fail(S5D_EINVAL, "desc->struct_size too small");
+  const s5d_desc& d = *desc;
+  if (d.ndim != 2 && d.ndim != 3) return fail(S5D_EINVAL, "ndim must be 2 or 3");
+  if (d.radius < 1) return fail(S5D_EINVAL, "radius must be >= 1");
+  if (d.shape != S5D_STAR && d.shape != S5D_BOX) return fail(S5D_EINVAL, "shape must be S5D_STAR or S5D_BOX");
+  if (d.dtype != S5D_F32 && d.dtype != S5D_F64) return fail(S5D_EINVAL, "dtype must be S5D_F32 or S5D_F64");
+  if (d.accum != S5D_ACC_PLAIN && d.accum != S5D_ACC_COMPENSATED)
+    return fail(S5D_EINVAL, "accum must be S5D_ACC_PLAIN or S5D_ACC_COMPENSATED");
+  if (d.accum == S5D_ACC_COMPENSATED && d.dtype != S5D_F32)
+    return fail(S5D_EINVAL, "compensated accumulation is defined for float32 grids only");
+  if (d.steps < 0) return fail(S5D_EINVAL, "steps must be >= 0");
+  if (d.radius > 64) return fail(S5D_EINVAL, "radius out of range");
+  int64_t n_expected = d.shape == S5D_BOX ? 1 : 2LL * d.radius * d.ndim + 1;
+  if (d.shape == S5D_BOX)
+    for (int a = 0; a < d.ndim; ++a) n_expected *= 2LL * d.radius + 1;
+  if (d.n_coeffs != n_expected)
+    return fail(S5D_EINVAL, "n_coeffs is " + std::to_string(d.n_coeffs) + ", the stencil has " +
+                                std::to_string(n_expected) + " points");
+  if (!d.coeffs) return fail(S5D_EINVAL, "coeffs is NULL");
+  for (int64_t k = 0; k < d.n_coeffs; ++k)
+    if (!std::isfinite(d.coeffs[k])) return fail(S5D_EINVAL, "coefficient " + std::to_string(k) + " is not finite");
+  int64_t total = 1;
+  int64_t padded[3] = {1, 1, 1};
+  for (int a = 0; a < d.ndim; ++a) {
+    if (d.interior[a] < 1) return fail(S5D_EINVAL, "interior extents must be >= 1");
+    if (d.interior[a] > (1LL << 30)) return fail(S5D_EINVAL, "interior extent too large");
+    padded[a] = d.interior[a] + 2LL * d.radius;
+    total *= padded[a];
+    if (total > (1LL << 31) - 1) return fail(S5D_EUNSUPPORTED, "padded grid exceeds 2^31-1 cells");
+  }
+
+  s5d_tuning req;
+  std::memset(&req, 0, sizeof(req));
+  if (tuning) {
+    if (tuning->struct_size < sizeof(s5d_tuning)) return fail(S5D_EINVAL, "tuning->struct_size too small");
+    req = *tuning;
+    if (req.bt < 0 || req.tile0 < 0 || req.tile1 < 0 || req.stream_chunk < 0 || req.cells_per_lane < 0 ||
+        req.waves_per_eu < 0)
+      return fail(S5D_EINVAL, "tuning fields must be >= 0");
+    if (req.bt > 15) return fail(S5D_EINVAL, "bt must be <= 15");
+  }
+
+  if (d.radius > max_radius(d.ndim, d.shape))
+    return fail(S5D_EUNSUPPORTED, "no kernel for this dimensionality/shape/radius");
+  if (d.accum == S5D_ACC_COMPENSATED) return fail(S5D_EUNSUPPORTED, "no compensated-accumulation kernel built");
+
+  const int box = d.shape == S5D_BOX ? 1 : 0;
+  const int r = d.radius;
+  // cells per lane
+  int cpl = req.cells_per_lane;
+  if (req.tile0 > 0) {
+    if (req.tile0 % 64 != 0) return fail(S5D_EINVAL, "tile0 must be a multiple of 64 (one wave64 per tile)");
+    if (cpl > 0 && cpl * 64 != req.tile0) return fail(S5D_EINVAL, "tile0 != 64 * cells_per_lane");
+    cpl = req.tile0 / 64;
+  }
+  int bt = req.bt;
+  if (cpl == 0) {
+    // widest tile that still reaches the requested (or default) depth
+    const int want = bt > 0 ? bt : default_bt(d.dtype, box, r);
+    int best_cpl = 0, best_bt = 0;
+    for (int c : {4, 2, 8}) {
+      const int mb = std::min(want, max_bt2d(d.dtype, box, r, c));
+      if (mb > best_bt) {
+        best_bt = mb;
+        best_cpl = c;
+      }
+    }
+    if (best_cpl == 0) return fail(S5D_EUNSUPPORTED, "no kernel variant for this stencil");
+    cpl = best_cpl;
+  }
+  const int bt_cap = max_bt2d(d.dtype, box, r, cpl);
+  if (bt_cap == 0) return fail(S5D_EUNSUPPORTED, "no kernel with cells_per_lane=" + std::to_string(cpl));
+  if (bt == 0) bt = std::min(default_bt(d.dtype, box, r), bt_cap);
+  if (bt > bt_cap)
+    return fail(S5D_EUNSUPPORTED, "bt=" + std::to_string(bt) + " exceeds the deepest kernel built for this stencil (" +
+                                      std::to_string(bt_cap) + ")");
+  if (d.steps > 0 && bt > d.steps) bt = static_cast<int>(d.steps);
+
+  s5d_plan* p = new (std::nothrow) s5d_plan;
+  if (!p) return fail(S5D_ENOMEM, "plan allocation failed");
+  p->d = d;
+  try {
+    p->coeffs.assign(d.coeffs, d.coeffs + d.n_coeffs);
+  } catch (...) {
+    delete p;
+    return fail(S5D_ENOMEM, "coefficient copy failed");
+  }
+  p->d.coeffs = nullptr;
+  for (int a = 0; a < 3; ++a) p->padded[a] = padded[a];
+  p->elem = d.dtype == S5D_F32 ? 4 : 8;
+  p->bytes = total * p->elem;
+  for (int b = 0; b < 16; ++b) p->by_bt[b] = Kernel2D{nullptr, nullptr, 0, 0, 0};
+  for (int b = 1; b <= bt; ++b) {
+    const Entry2D* e = find2d(d.dtype, box, r, cpl, b);
+    if (!e) {
+      delete p;
+      return fail(S5D_EUNSUPPORTED, "kernel variant missing for bt=" + std::to_string(b));
+    }
+    p->by_bt[b] = e->make();
+  }
+
+  int chunk = req.stream_chunk;
+  if (chunk == 0) {
+    const DeviceInfo dev = query_device();
+    int occ = dev.ok ? p->by_bt[bt].occupancy() : 0;
+    if (occ <= 0) occ = 2;
+    const int64_t C = 64LL * cpl - 2LL * bt * r;
+    const int64_t ntiles = (d.interior[1] + C - 1) / C;
+    const int64_t slots = static_cast<int64_t>(dev.cus) * occ * s5d::kWavesPerBlock;
+    chunk = choose_chunk(d.interior[0], ntiles, slots, bt, r);
+  }
+  if (chunk < 1) {
+    delete p;
+    return fail(S5D_EINVAL, "stream_chunk must be >= 1");
+  }
+  std::memset(&p->tun, 0, sizeof(p->tun));
+  p->tun.struct_size = sizeof(s5d_tuning);
+  p->tun.bt = bt;
+  p->tun.tile0 = 64 * cpl;
+  p->tun.tile1 = 0;
+  p->tun.stream_chunk = chunk;
+  p->tun.cells_per_lane = cpl;
+  p->tun.waves_per_eu = 0;
+  *out = p;
+  return S5D_OK;
+}
+
+void s5d_plan_destroy(s5d_plan* plan) { delete plan; }
+
+s5d_status s5d_plan_query(const s5d_plan* plan, s5d_tuning* chosen, int64_t* bytes_per_buffer) {
+  if (!plan) return fail(S5D_EINVAL, "plan is NULL");
+  if (chosen) {
+    if (chosen->struct_size != 0 && chosen->struct_size < sizeof(s5d_tuning))
+      return fail(S5D_EINVAL, "chosen->struct_size too small");
+    *chosen = plan->tun;
+  }
+  if (bytes_per_buffer) *bytes_per_buffer = plan->bytes;
+  return S5D_OK;
+}
+
+s5d_status s5d_run(const s5d_plan* plan, void* buf0, void* buf1, void* stream, int32_t* result_index) {
+  g_last_error.clear();
+  if (!plan) return fail(S5D_EINVAL, "plan is NULL");
+  if (!buf0 || !buf1) return fail(S5D_EINVAL, "buffer pointer is NULL");
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(buf0), a1 = reinterpret_cast<uintptr_t>(buf1);
+  const uintptr_t nb = static_cast<uintptr_t>(plan->bytes);
+  if (a0 < a1 + nb && a1 < a0 + nb) return fail(S5D_EINVAL, "buffers overlap");
+  if (a0 % plan->elem != 0 || a1 % plan->elem != 0) return fail(S5D_EINVAL, "buffers not aligned to the element size");
+  const int64_t T = plan->d.steps;
+  if (result_index) *result_index = static_cast<int32_t>(T % 2);
+  if (T == 0) return S5D_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  hipError_t e = s5d::launch_halo_copy(buf0, buf1, plan->elem, plan->d.ndim, plan->padded, plan->d.radius, st);
+  if (e != hipSuccess) return device_fail(e, "boundary copy launch");
+
+  const RoundSchedule rs = schedule_rounds(T, plan->tun.bt);
+  s5d::Round2D rd;
+  rd.I0 = static_cast<int32_t>(plan->d.interior[0]);
+  rd.I1 = static_cast<int32_t>(plan->d.interior[1]);
+  rd.chunk = plan->tun.stream_chunk;
+  rd.coeffs = plan->coeffs.data();
+  rd.stream = st;
+  void* bufs[2] = {buf0, buf1};
+  int64_t k = 0;
+  auto one = [&](int bt) -> hipError_t {
+    rd.src = bufs[k % 2];
+    rd.dst = bufs[(k + 1) % 2];
+    ++k;
+    return plan->by_bt[bt].launch(rd);
+  };
+  for (int64_t i = 0; i < rs.n_full; ++i) {
+    e = one(rs.bt);
+    if (e != hipSuccess) return device_fail(e, "sweep launch");
+  }
+  for (int i = 0; i < rs.n_tail; ++i) {
+    e = one(rs.tail[i]);
+    if (e != hipSuccess) return device_fail(e, "sweep launch");
+  }
+  return S5D_OK;
+}
+
+}  // extern "C"

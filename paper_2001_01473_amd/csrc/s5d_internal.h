@@ -1,0 +1,73 @@
+// Internal interfaces shared by the host scheduler and the kernel units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace s5d {
+
+// Stencil points: star 2*r*d + 1, box (2r+1)^d (AN5D Table 3).
+constexpr int npts(int ndim, int r, bool box) {
+  return box ? (ndim == 2 ? (2 * r + 1) * (2 * r + 1) : (2 * r + 1) * (2 * r + 1) * (2 * r + 1))
+             : 2 * r * ndim + 1;
+}
+
+// Coefficients travel by value in the kernel arguments, so they are loaded
+// into scalar registers once per wave and feed every FMA as an SGPR operand.
+template <typename T, int N>
+struct CoefPack {
+  T c[N];
+};
+
+// Everything one launch of a 2D round needs besides the coefficients.
+struct Round2D {
+  const void* src;
+  void* dst;
+  int32_t I0, I1;   // interior extents (axis 0 streams)
+  int32_t chunk;    // h_SN: output rows per stream block
+  const double* coeffs;
+  hipStream_t stream;
+};
+
+// Geometry of one 2D launch, derived on the host.
+struct Sweep2DArgs {
+  const void* src;
+  void* dst;
+  int32_t I0, I1;
+  int32_t ntiles;   // tiles across axis 1
+  int32_t nwaves;   // ntiles * stream blocks
+  int32_t chunk;    // h_SN
+  int32_t pad;
+};
+
+using Launch2DFn = hipError_t (*)(const Round2D&);
+using Occupancy2DFn = int (*)();   // resident workgroups per CU (0 if unknown)
+
+struct Kernel2D {
+  Launch2DFn launch;
+  Occupancy2DFn occupancy;
+  int cpl;       // cells per lane
+  int bt;        // fused time steps
+  int tile;      // 64 * cpl
+};
+
+// One compiled 2D kernel variant.  The build enumerates the variants (one
+// object file each) and writes the table kRegistry2D.
+struct Entry2D {
+  int dtype;   // 0 = float32, 1 = float64
+  int box;     // 0 = star, 1 = box
+  int r;
+  int cpl;
+  int bt;
+  Kernel2D (*make)();
+};
+extern const Entry2D kRegistry2D[];
+extern const int kRegistry2DSize;
+
+// Copy the boundary cells (width r on every face) of a padded grid.
+hipError_t launch_halo_copy(const void* src, void* dst, int elem_bytes, int ndim,
+                            const int64_t* padded, int r, hipStream_t stream);
+
+constexpr int kWavesPerBlock = 4;
+
+}  // namespace s5d

@@ -1,0 +1,155 @@
+"""C ABI checks that need no GPU: exported symbols and host-side validation.
+
+No test here launches a kernel: every call either fails validation before
+any HIP call, or is a T = 0 sweep, which enqueues nothing.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "stencil5d.h")
+
+from paper_2001_01473_amd import _lib  # noqa: E402
+
+pytestmark = pytest.mark.skipif(not os.path.exists(_lib.LIB_PATH),
+                                reason="libstencil5d.so not built")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(s5d_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_binding_exports():
+    assert declared_symbols() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_package_import_does_not_load_oracle():
+    import sys
+    import paper_2001_01473_amd  # noqa: F401
+    mod = sys.modules["paper_2001_01473_amd"]
+    assert "oracle" not in getattr(mod, "__dict__", {})
+    src = open(os.path.join(ROOT, "paper_2001_01473_amd", "__init__.py")).read()
+    src += open(os.path.join(ROOT, "paper_2001_01473_amd", "_lib.py")).read()
+    assert "import oracle" not in src and "from oracle" not in src
+
+
+def _create(ndim=2, radius=1, box=False, dtype=_lib.F64, accum=0, interior=(64, 64),
+            steps=4, coeffs=None, tuning=None, n_coeffs=None):
+    lib = _lib.load()
+    if coeffs is None:
+        n = (2 * radius + 1) ** ndim if box else 2 * radius * ndim + 1
+        coeffs = np.full(n, 1.0 / n)
+    d, keep = _lib.make_desc(ndim, radius, box, dtype, accum, interior, steps, coeffs)
+    if n_coeffs is not None:
+        d.n_coeffs = n_coeffs
+    h = ctypes.c_void_p()
+    st = lib.s5d_plan_create(ctypes.byref(d), ctypes.byref(tuning) if tuning else None,
+                             ctypes.byref(h))
+    return st, h
+
+
+FULL = dict(bt=2, stream_chunk=32, cells_per_lane=4)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(ndim=4), _lib.S5D_EINVAL),
+    (dict(ndim=1), _lib.S5D_EINVAL),
+    (dict(radius=0), _lib.S5D_EINVAL),
+    (dict(steps=-1), _lib.S5D_EINVAL),
+    (dict(n_coeffs=4), _lib.S5D_EINVAL),
+    (dict(interior=(0, 5)), _lib.S5D_EINVAL),
+    (dict(dtype=7), _lib.S5D_EINVAL),
+    (dict(accum=1, dtype=_lib.F64), _lib.S5D_EINVAL),
+    (dict(coeffs=np.array([0.2, 0.2, np.nan, 0.2, 0.2])), _lib.S5D_EINVAL),
+    (dict(radius=3, box=True), _lib.S5D_EUNSUPPORTED),
+    (dict(radius=5), _lib.S5D_EUNSUPPORTED),
+])
+def test_plan_create_rejects(kw, code):
+    st, h = _create(tuning=_lib.make_tuning(**FULL), **kw)
+    assert st == code, (_lib.status_string(st), _lib.last_error())
+    assert h.value is None
+    assert _lib.last_error() != ""
+
+
+def test_plan_create_rejects_bad_tuning():
+    st, _ = _create(tuning=_lib.make_tuning(bt=-1))
+    assert st == _lib.S5D_EINVAL
+    st, _ = _create(tuning=_lib.make_tuning(tile0=100, stream_chunk=8))
+    assert st == _lib.S5D_EINVAL
+    st, _ = _create(tuning=_lib.make_tuning(bt=15, stream_chunk=8, cells_per_lane=4))
+    assert st == _lib.S5D_EUNSUPPORTED
+    bad = _lib.make_tuning(**FULL)
+    bad.struct_size = 4
+    st, _ = _create(tuning=bad)
+    assert st == _lib.S5D_EINVAL
+
+
+def test_null_arguments():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.s5d_plan_create(None, None, ctypes.byref(h)) == _lib.S5D_EINVAL
+    d, keep = _lib.make_desc(2, 1, False, _lib.F64, 0, (8, 8), 1, np.full(5, 0.2))
+    assert lib.s5d_plan_create(ctypes.byref(d), None, None) == _lib.S5D_EINVAL
+    d.struct_size = 8
+    assert lib.s5d_plan_create(ctypes.byref(d), None, ctypes.byref(h)) == _lib.S5D_EINVAL
+    assert lib.s5d_plan_query(None, None, None) == _lib.S5D_EINVAL
+    assert lib.s5d_run(None, None, None, None, None) == _lib.S5D_EINVAL
+    lib.s5d_plan_destroy(None)
+
+
+def test_plan_query_and_run_validation():
+    lib = _lib.load()
+    st, h = _create(interior=(100, 300), steps=7, tuning=_lib.make_tuning(**FULL))
+    assert st == _lib.S5D_OK, _lib.last_error()
+    t = _lib.make_tuning()
+    nb = ctypes.c_int64()
+    assert lib.s5d_plan_query(h, ctypes.byref(t), ctypes.byref(nb)) == _lib.S5D_OK
+    assert (t.bt, t.stream_chunk, t.cells_per_lane, t.tile0) == (2, 32, 4, 256)
+    assert nb.value == 102 * 302 * 8
+    idx = ctypes.c_int32(-1)
+    # null, overlapping and misaligned buffers are refused before any HIP call
+    assert lib.s5d_run(h, None, ctypes.c_void_p(4096), None, ctypes.byref(idx)) == _lib.S5D_EINVAL
+    assert lib.s5d_run(h, ctypes.c_void_p(1 << 20), ctypes.c_void_p((1 << 20) + 64), None,
+                       ctypes.byref(idx)) == _lib.S5D_EINVAL
+    assert lib.s5d_run(h, ctypes.c_void_p((1 << 24) + 4), ctypes.c_void_p(1 << 28), None,
+                       ctypes.byref(idx)) == _lib.S5D_EINVAL
+    lib.s5d_plan_destroy(h)
+
+
+def test_zero_steps_enqueues_nothing():
+    lib = _lib.load()
+    st, h = _create(steps=0, tuning=_lib.make_tuning(**FULL))
+    assert st == _lib.S5D_OK
+    idx = ctypes.c_int32(-1)
+    # fake, never dereferenced addresses: T = 0 makes no HIP call at all
+    assert lib.s5d_run(h, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 28), None,
+                       ctypes.byref(idx)) == _lib.S5D_OK
+    assert idx.value == 0
+    lib.s5d_plan_destroy(h)
+
+
+def test_bt_clamped_to_steps():
+    lib = _lib.load()
+    st, h = _create(steps=3, tuning=_lib.make_tuning(bt=8, stream_chunk=16, cells_per_lane=4))
+    assert st == _lib.S5D_OK
+    t = _lib.make_tuning()
+    lib.s5d_plan_query(h, ctypes.byref(t), None)
+    assert t.bt == 3
+    lib.s5d_plan_destroy(h)
+
+
+def test_status_strings():
+    assert _lib.status_string(_lib.S5D_OK) == "S5D_OK"
+    assert _lib.status_string(_lib.S5D_EUNSUPPORTED) == "S5D_EUNSUPPORTED"
+    assert _lib.status_string(99) == "S5D_UNKNOWN"
