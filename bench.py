@@ -130,21 +130,24 @@ def time_steps(prob, steps, warmup):
 
 
 def time_one_round(r, box, dtype, bt, launches=20, **tuning):
-    """Average duration of one launch of the b_T kernel (one round), HIP events."""
+    """Average duration of one launch of the b_T kernel (one round), HIP events.
+
+    A plan of 2*b_T steps is exactly two full rounds (an even round count, as
+    the result parity requires), so each run is one tiny boundary copy plus
+    two launches of the b_T kernel."""
     import torch
-    prob = Problem(r, box, dtype, steps=bt, bt=bt, **tuning)
+    prob = Problem(r, box, dtype, steps=2 * bt, bt=bt, **tuning)
     for _ in range(3):
         prob.run()
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
-    # steps = bt: each run is one boundary copy (tiny) plus one sweep launch
     a.record()
     for _ in range(launches):
         prob.run()
     b.record()
     b.synchronize()
-    dt = a.elapsed_time(b) / 1e3 / launches
+    dt = a.elapsed_time(b) / 1e3 / (2 * launches)
     info = prob.info
     prob.close()
     return dt, info
@@ -189,10 +192,11 @@ def cpu_baseline(r, box, dtype, target_s=12.0):
     rng = np.random.default_rng(si.workload_seed(1))
     c = si.random_coeffs(rng, npts(r, box))
     g = rng.random(si.padded_shape((N, N), r)).astype(np.float32 if dtype == "f32" else np.float64)
+    oracle.sweep(g, radius=r, box=box, coeffs=c, steps=1)  # warm-up: first touch of the pages
     t0 = time.perf_counter()
-    oracle.sweep(g, radius=r, box=box, coeffs=c, steps=1)
-    one = time.perf_counter() - t0
-    steps = int(max(2, min(40, target_s / max(one, 1e-3))))
+    oracle.sweep(g, radius=r, box=box, coeffs=c, steps=4)
+    one = (time.perf_counter() - t0) / 4
+    steps = int(max(2, min(T_STEPS, target_s / max(one, 1e-3))))
     t0 = time.perf_counter()
     oracle.sweep(g, radius=r, box=box, coeffs=c, steps=steps)
     dt = time.perf_counter() - t0
@@ -202,22 +206,105 @@ def cpu_baseline(r, box, dtype, target_s=12.0):
                 stencil_name(r, box), dtype, N, N, steps, T_STEPS, dt)}
 
 
+def full_sweep():
+    """Every compiled 2D variant at 16384^2, T = 1000 (one warm-up, one timed run)."""
+    import torch
+    from paper_2001_01473_amd import build as lib_build
+    for dtype_code, box, r, cpl, bt, nr in lib_build.variants_2d():
+        dtype = "f32" if dtype_code == 0 else "f64"
+        try:
+            p = Problem(r, bool(box), dtype, bt=bt, cells_per_lane=cpl)
+        except Exception as e:  # noqa: BLE001 - reported, not fatal
+            print(json.dumps({"stencil": stencil_name(r, box), "dtype": dtype, "bt": bt,
+                              "cpl": cpl, "error": str(e)[:120]}), flush=True)
+            continue
+        s = time_steps(p, 1, 1)
+        g = N * N * T_STEPS / s / 1e9
+        print(json.dumps({"stencil": stencil_name(r, box), "dtype": dtype, "bt": bt, "cpl": cpl,
+                          "stream_chunk": p.info["stream_chunk"], "gcells": round(g, 1)}),
+              flush=True)
+        p.close()
+        torch.cuda.empty_cache()
+
+
+def ingest_counters(fetch_dir, write_dir, out_json, out_md, command):
+    """Per-launch HBM traffic of the headline kernel from two rocprofv3 --pmc
+    runs of `bench.py --probe` (FETCH_SIZE, then WRITE_SIZE), each scaled by what
+    the same counter reads for the probe's copy of known size."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            rows += [r for r in csv.DictReader(open(f)) if r["Counter_Name"] == counter]
+        kern = [float(r["Counter_Value"]) for r in rows if "sweep2d_kernel" in r["Kernel_Name"]]
+        # the copy of known size is torch's elementwise add kernel
+        copy = [float(r["Counter_Value"]) for r in rows if "add" in r["Kernel_Name"].lower()
+                and "sweep2d" not in r["Kernel_Name"]]
+        if not kern or not copy:
+            raise SystemExit("no %s records in %s" % (counter, d))
+        return sum(kern) / len(kern), max(copy), len(kern)
+
+    copy_bytes = float(PROBE_COPY_BYTES)
+    kf, cf, nk = load(fetch_dir, "FETCH_SIZE")
+    kw, cw, _ = load(write_dir, "WRITE_SIZE")
+    f_scale = copy_bytes / (cf * 1024.0)
+    w_scale = copy_bytes / (cw * 1024.0)
+    read_b = kf * 1024.0 * f_scale
+    write_b = kw * 1024.0 * w_scale
+    rec = {"kernel": "sweep2d star r=1 f32 bt=%d 16384^2" % PROBE_BT, "bt": PROBE_BT,
+           "kernel_hash": kernel_source_hash(),
+           "fetch_size_kib_per_launch": kf, "write_size_kib_per_launch": kw,
+           "copy_fetch_kib": cf, "copy_write_kib": cw, "copy_bytes_each_way": copy_bytes,
+           "fetch_scale": f_scale, "write_scale": w_scale, "launches": nk,
+           "hbm_read_bytes_per_launch": read_b, "hbm_write_bytes_per_launch": write_b,
+           "hbm_bytes_per_launch": read_b + write_b,
+           "algorithmic_bytes_per_launch": 2.0 * 4 * N * N, "command": command}
+    with open(out_json, "w") as f:
+        json.dump(rec, f, indent=1)
+    with open(out_md, "w") as f:
+        f.write("# HBM traffic: sweep2d star r=1 float32 b_T=%d, 16384^2 interior\n\n" % PROBE_BT)
+        f.write("Commands (run from the repository root):\n\n```\n%s\n```\n\n" % command)
+        f.write("| counter | kernel (KiB/launch) | copy of %.0f MiB (KiB) | scale | bytes/launch |\n"
+                % (copy_bytes / 2**20))
+        f.write("|---|---|---|---|---|\n")
+        f.write("| FETCH_SIZE | %.0f | %.0f | %.3f | %.3e |\n" % (kf, cf, f_scale, read_b))
+        f.write("| WRITE_SIZE | %.0f | %.0f | %.3f | %.3e |\n" % (kw, cw, w_scale, write_b))
+        f.write("\nAlgorithmic bytes per launch (one read + one write of the 16386^2 "
+                "float32 grid, interior only counted): %.3e.  Measured / algorithmic = %.2f.\n"
+                % (2.0 * 4 * N * N, (read_b + write_b) / (2.0 * 4 * N * N)))
+    print(json.dumps(rec))
+
+
+PROBE_BT = 10
+PROBE_COPY_BYTES = 1 << 30
+
+
 def probe(args):
     """Launches for rocprofv3 counter runs: a copy of known size, then the kernel."""
     import torch
-    nbytes = 1 << 30
+    nbytes = PROBE_COPY_BYTES
     x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").uniform_()
     y = torch.empty_like(x)
     torch.cuda.synchronize()
-    for _ in range(3):
-        y.copy_(x)
+    # the copy of known size: y = x + x reads x once and writes y once
+    torch.add(x, x, out=y)
     torch.cuda.synchronize()
     print("probe copy bytes_read=%d bytes_written=%d" % (nbytes, nbytes), flush=True)
-    prob = Problem(1, False, "f32", steps=args.bt, bt=args.bt)
+    del x, y
+    import paper_2001_01473_amd as s5d
+    shape = si.padded_shape((N, N), 1)
+    b0 = torch.full(shape, 0.5, dtype=torch.float32, device="cuda:0")
+    b1 = torch.empty_like(b0)
+    # 2*b_T steps = two launches of the b_T kernel per run
+    plan = s5d.Plan(ndim=2, radius=1, box=False, dtype="f32", interior=(N, N), steps=2 * args.bt,
+                    coeffs=si.random_coeffs(np.random.default_rng(si.workload_seed(1)), 5),
+                    bt=args.bt)
     for _ in range(args.launches):
-        prob.run()
+        plan.run(b0, b1)
     torch.cuda.synchronize()
-    print("probe kernel %s launches=%d" % (json.dumps(prob.info), args.launches), flush=True)
+    print("probe kernel %s runs=%d" % (json.dumps(plan.query()), args.launches), flush=True)
 
 
 def main(argv=None):
@@ -229,8 +316,18 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--bt", type=int, default=0, help="force b_T for the headline run")
     ap.add_argument("--probe", action="store_true")
-    ap.add_argument("--launches", type=int, default=5)
+    ap.add_argument("--full-sweep", action="store_true",
+                    help="time every compiled (stencil, dtype, b_T, cells per lane) at the "
+                         "benchmark size and print one JSON line per variant")
+    ap.add_argument("--launches", type=int, default=3)
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc runs of --probe into the traffic record")
+    ap.add_argument("--command", default="", help="command line recorded with --ingest-counters")
     args = ap.parse_args(argv)
+    if args.ingest_counters:
+        ingest_counters(args.ingest_counters[0], args.ingest_counters[1], TRAFFIC_RECORD,
+                        TRAFFIC_RECORD.replace(".json", ".md"), args.command)
+        return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the stencil sweep here runs on a single MI355X "
               "(multi-GPU sharding is described, not built); use --gpus 1", file=sys.stderr)
@@ -241,8 +338,11 @@ def main(argv=None):
         return 2
     if args.probe:
         if args.bt == 0:
-            args.bt = 10
+            args.bt = PROBE_BT
         probe(args)
+        return 0
+    if args.full_sweep:
+        full_sweep()
         return 0
 
     tuning = {"bt": args.bt} if args.bt else {}

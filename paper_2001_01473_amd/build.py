@@ -7,9 +7,12 @@ plus a registry table into ``_build/``, compiles them in parallel and links
 everything with the host code into ``libstencil5d.so`` next to this file.
 
 Variant pruning follows the spirit of AN5D's register pruning ("Tuning"):
-a variant is built only if its register window fits in the 256 architected
-VGPRs of a gfx950 lane and its compute region keeps at least a quarter of the
-tile width.
+candidates whose compute region keeps at least a quarter of the tile width and
+whose register state plausibly fits are compiled, and only those that the
+compiler fits into the 256 architected VGPRs of a gfx950 lane without scratch
+memory (at most 128 accumulation registers used as spill space) enter the
+library.  Each variant's
+resource report (VGPRs, occupancy, LDS) is kept in kernel_resources.json.
 
 Usage: ``python -m paper_2001_01473_amd.build [--jobs N] [--incremental]``.
 """
@@ -45,16 +48,25 @@ DTYPES = {0: ("f32", "float", 1), 1: ("f64", "double", 2)}
 MAX_BT = 10
 
 
-def est_vgprs_2d(words, box, r, cpl, bt, pfk):
-    """Register window estimate of one 2D variant, in 32-bit VGPRs."""
-    u = 2 * r + 1
-    nx = 2 * r if box else 0
-    stage = u * pfk * cpl
-    return words * (bt * u * (cpl + nx) + stage + cpl + 2 * r) + 24
+def est_vgprs_2d(words, box, r, cpl, bt, nr):
+    """Lower bound of the register state of one 2D variant, in 32-bit VGPRs:
+    2r accumulator rows per level, the load ring, the extended row."""
+    return words * (bt * 2 * r * cpl + nr * cpl + cpl + 2 * r) + 16
 
 
-def variants_2d():
-    """(dtype, box, r, cpl, bt, pfk) tuples that get compiled."""
+def ring_depth(r, bt, words):
+    """Rows in the load ring (NR - 1 in flight): 4 for deep kernels, 8 when the
+    kernel is shallow (b_T <= 2) and therefore bound by memory latency; a
+    divisor or multiple of 2r so the unrolled loop stays lcm(2r, NR) <= 8."""
+    if r == 3:
+        return 6 if bt <= 2 and words == 1 else 3
+    if bt <= 2 and not (words == 2 and r >= 3):
+        return 8
+    return 4
+
+
+def candidates_2d():
+    """(dtype, box, r, cpl, bt, nr) tuples worth compiling."""
     out = []
     for dtype, (_, _, words) in DTYPES.items():
         cpls = (4,) if dtype == 0 else (2, 4)
@@ -66,19 +78,56 @@ def variants_2d():
                     for bt in range(1, MAX_BT + 1):
                         if 64 * cpl - 2 * bt * r < 16 * cpl:
                             continue
-                        pfk = 1 if r <= 2 else 0
-                        if est_vgprs_2d(words, box, r, cpl, bt, pfk) > 256:
-                            pfk = 0
-                        if est_vgprs_2d(words, box, r, cpl, bt, pfk) > 256:
+                        nr = ring_depth(r, bt, words)
+                        if est_vgprs_2d(words, box, r, cpl, bt, nr) > 224:
                             continue
-                        out.append((dtype, box, r, cpl, bt, pfk))
+                        out.append((dtype, box, r, cpl, bt, nr))
+    return out
+
+
+def variants_2d():
+    """Variants in the built library: the candidates the compiler fitted into
+    registers without scratch spills (read from the last build's resource
+    record), or all candidates if there is no record yet."""
+    rec = _load_resources()
+    if not rec:
+        return candidates_2d()
+    return [v for v in candidates_2d() if _vname(v) in rec and rec[_vname(v)]["ok"]]
+
+
+RESOURCES = os.path.join(HERE, "kernel_resources.json")
+
+
+def _load_resources():
+    if not os.path.exists(RESOURCES):
+        return {}
+    import json
+    with open(RESOURCES) as f:
+        return json.load(f)
+
+
+_RES_KEYS = {"VGPRs": "vgprs", "AGPRs": "agprs", "ScratchSize [bytes/lane]": "scratch",
+             "Occupancy [waves/SIMD]": "occupancy", "LDS Size [bytes/block]": "lds",
+             "SGPRs": "sgprs"}
+
+
+def _parse_resources(text):
+    """Kernel resource remarks of one compile (one kernel per unit)."""
+    import re
+    out = {}
+    for line in text.splitlines():
+        m = re.search(r"remark:.*?\s(VGPRs|AGPRs|SGPRs|ScratchSize \[bytes/lane\]|"
+                      r"Occupancy \[waves/SIMD\]|LDS Size \[bytes/block\]): (\d+) \[-Rpass-analysis",
+                      line)
+        if m:
+            out[_RES_KEYS[m.group(1)]] = int(m.group(2))
     return out
 
 
 def _vname(v):
-    dtype, box, r, cpl, bt, pfk = v
-    return "k2d_%s_%s_r%d_c%d_b%d_p%d" % (DTYPES[dtype][0], "box" if box else "star",
-                                          r, cpl, bt, pfk)
+    dtype, box, r, cpl, bt, nr = v
+    return "k2d_%s_%s_r%d_c%d_b%d_n%d" % (DTYPES[dtype][0], "box" if box else "star",
+                                          r, cpl, bt, nr)
 
 
 def _write_if_changed(path, text):
@@ -95,11 +144,11 @@ def _generate(variants):
     os.makedirs(inst, exist_ok=True)
     units = []
     for v in variants:
-        dtype, box, r, cpl, bt, pfk = v
+        dtype, box, r, cpl, bt, nr = v
         name = _vname(v)
         text = ('#include "sweep2d.h"\nnamespace s5d {\nKernel2D %s() {\n'
                 '  return make_kernel2d<%s, %d, %s, %d, %d, %d>();\n}\n}  // namespace s5d\n'
-                % (name, DTYPES[dtype][1], r, "true" if box else "false", bt, cpl, pfk))
+                % (name, DTYPES[dtype][1], r, "true" if box else "false", bt, cpl, nr))
         path = os.path.join(inst, name + ".hip")
         _write_if_changed(path, text)
         units.append(path)
@@ -107,7 +156,7 @@ def _generate(variants):
     lines += ["Kernel2D %s();" % _vname(v) for v in variants]
     lines.append("const Entry2D kRegistry2D[] = {")
     for v in variants:
-        dtype, box, r, cpl, bt, pfk = v
+        dtype, box, r, cpl, bt, nr = v
         lines.append("  {%d, %d, %d, %d, %d, &%s}," % (dtype, box, r, cpl, bt, _vname(v)))
     lines.append("};")
     lines.append("const int kRegistry2DSize = %d;" % len(variants))
@@ -127,53 +176,84 @@ def _digest(paths, extra):
 
 
 def _compile(src, header_digest, incremental):
+    """Compile one unit; returns (object path, seconds, kernel resources)."""
+    import json
     base = os.path.splitext(os.path.basename(src))[0]
-    key = _digest([src], DEVICE_FLAGS + [header_digest, "v2"])
+    key = _digest([src], DEVICE_FLAGS + [header_digest, "v5"])
     obj = os.path.join(BUILD, "obj", "%s.%s.o" % (base, key))
-    if incremental and os.path.exists(obj):
-        return obj, 0.0
+    meta = obj + ".res.json"
+    if incremental and os.path.exists(obj) and os.path.exists(meta):
+        with open(meta) as f:
+            return obj, 0.0, json.load(f)
     os.makedirs(os.path.dirname(obj), exist_ok=True)
     tmp = obj + ".tmp%d" % os.getpid()
     t0 = time.time()
     host_only = src.endswith(".cpp")  # plain host code: no device pass
-    cmd = [HIPCC, *DEVICE_FLAGS, *(["--offload-host-only"] if host_only else []),
+    cmd = [HIPCC, *DEVICE_FLAGS, *(["--offload-host-only"] if host_only
+                                   else ["-Rpass-analysis=kernel-resource-usage"]),
            "-c", src, "-o", tmp]
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s" % (src, res.stdout))
     os.replace(tmp, obj)
-    return obj, time.time() - t0
+    resources = _parse_resources(res.stdout)
+    with open(meta, "w") as f:
+        json.dump(resources, f)
+    return obj, time.time() - t0, resources
 
 
-def build(jobs: int | None = None, incremental: bool = False, verbose: bool = False) -> str:
-    """Compile every kernel variant and link libstencil5d.so; returns its path."""
+def build(jobs: int | None = None, incremental: bool = False, verbose: bool = False,
+          only: str | None = None) -> str:
+    """Compile every candidate kernel variant, keep those without register
+    spills, write the registry and link libstencil5d.so; returns its path.
+    `only` (a regular expression over variant names) builds a subset, for
+    kernel development."""
+    import json
+    import re
     if not incremental and os.path.isdir(os.path.join(BUILD, "obj")):
         shutil.rmtree(os.path.join(BUILD, "obj"))
-    variants = variants_2d()
-    units, reg = _generate(variants)
+    cands = [v for v in candidates_2d() if only is None or re.search(only, _vname(v))]
+    units, _ = _generate(cands)
     hdr = _digest([os.path.join(CSRC, h) for h in HEADERS] +
                   [os.path.join(INCLUDE, "stencil5d.h")], [])
-    sources = [os.path.join(CSRC, s) for s in HOST_SOURCES] + [reg] + units
-    # longest first: the box and deep variants dominate the build time
-    sources.sort(key=lambda p: (("box" not in p), -len(p)))
     jobs = jobs or max(1, min(32, os.cpu_count() or 1))
     t0 = time.time()
-    objs = []
+    objs, res_by_unit = {}, {}
+    host = [os.path.join(CSRC, s) for s in HOST_SOURCES]
+    # longest first: the box and deep variants dominate the build time
+    order = sorted(units, key=lambda p: (("box" not in p), -len(p))) + host
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        futs = {ex.submit(_compile, s, hdr, incremental): s for s in sources}
+        futs = {ex.submit(_compile, s, hdr, incremental): s for s in order}
         for fut in cf.as_completed(futs):
-            obj, dt = fut.result()
-            objs.append(obj)
+            obj, dt, resources = fut.result()
+            src = futs[fut]
+            objs[src] = obj
+            res_by_unit[os.path.splitext(os.path.basename(src))[0]] = resources
             if verbose and dt > 0:
-                print("  %-60s %6.1f s" % (os.path.basename(futs[fut]), dt), flush=True)
+                print("  %-44s %6.1f s  %s" % (os.path.basename(src), dt, resources), flush=True)
+    record = {}
+    for v in cands:
+        r = dict(res_by_unit.get(_vname(v), {}))
+        # no scratch memory; accumulation registers used as spill space are
+        # tolerated (they cost register copies, not memory traffic)
+        r["ok"] = r.get("scratch", 1) == 0 and r.get("vgprs", 999) <= 256 and r.get("agprs", 0) <= 128
+        record[_vname(v)] = r
+    kept = [v for v in cands if record[_vname(v)]["ok"]]
+    _, reg = _generate(kept)
+    reg_obj, _, _ = _compile(reg, hdr, False)
+    with open(RESOURCES, "w") as f:
+        json.dump(record, f, indent=1, sort_keys=True)
+    link = [objs[s] for s in host] + [reg_obj] + \
+        [objs[os.path.join(BUILD, "inst", _vname(v) + ".hip")] for v in kept]
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *sorted(objs)]
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *link]
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed:\n" + res.stdout)
     os.replace(tmp, LIB)
     if verbose:
-        print("built %s: %d kernel variants in %.0f s" % (LIB, len(variants), time.time() - t0))
+        print("built %s: %d of %d candidate variants fit in registers, %.0f s"
+              % (LIB, len(kept), len(cands), time.time() - t0))
     return LIB
 
 
@@ -183,12 +263,14 @@ def main(argv=None):
     ap.add_argument("--incremental", action="store_true",
                     help="reuse object files whose sources and flags are unchanged")
     ap.add_argument("--list", action="store_true", help="print the variant set and exit")
+    ap.add_argument("--only", default=None, help="regular expression: build matching variants only")
     args = ap.parse_args(argv)
     if args.list:
-        for v in variants_2d():
-            print(_vname(v))
+        rec = _load_resources()
+        for v in candidates_2d():
+            print(_vname(v), rec.get(_vname(v), {}))
         return 0
-    build(jobs=args.jobs, incremental=args.incremental, verbose=True)
+    build(jobs=args.jobs, incremental=args.incremental, verbose=True, only=args.only)
     return 0
 
 

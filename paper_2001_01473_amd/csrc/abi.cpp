@@ -54,15 +54,23 @@ int max_bt2d(int dtype, int box, int r, int cpl) {
   return best;
 }
 
-// Starting point when the caller leaves b_T to the library: deep blocking for
-// low-order stencils, shallower for high-order and box ones, where the
-// per-level work and the register window grow (AN5D "Scaling Performance").
-int default_bt(int dtype, int box, int r) {
-  static const int f32_star[4] = {10, 8, 6, 5}, f32_box[2] = {8, 4};
-  static const int f64_star[4] = {8, 6, 4, 4}, f64_box[2] = {6, 3};
+// Defaults when the caller leaves b_T and the cells per lane to the library:
+// the best pair measured on MI355X at 16384^2, T = 1000, per (dtype, shape,
+// radius).  Low-order stencils take deep temporal blocking (AN5D "Scaling
+// Performance"); high-order and box stencils shallower, where the per-level
+// work and the register window grow.
+struct Default2D {
+  int bt, cpl;
+};
+Default2D default_tuning(int dtype, int box, int r) {
+  static const Default2D f32_star[4] = {{10, 4}, {7, 4}, {4, 4}, {3, 4}};
+  static const Default2D f32_box[2] = {{6, 4}, {3, 4}};
+  static const Default2D f64_star[4] = {{9, 2}, {4, 2}, {3, 4}, {2, 4}};
+  static const Default2D f64_box[2] = {{8, 2}, {3, 2}};
   if (dtype == S5D_F32) return box ? f32_box[r - 1] : f32_star[r - 1];
   return box ? f64_box[r - 1] : f64_star[r - 1];
 }
+int default_bt(int dtype, int box, int r) { return default_tuning(dtype, box, r).bt; }
 
 struct DeviceInfo {
   int cus = 256;
@@ -212,6 +220,11 @@ s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_p
     if (total > (1LL << 31) - 1) return fail(S5D_EUNSUPPORTED, "padded grid exceeds 2^31-1 cells");
   }
 
+  // kernels address one padded row through a buffer descriptor whose range
+  // is a 32-bit byte count
+  if (padded[d.ndim - 1] * (d.dtype == S5D_F32 ? 4 : 8) >= (1LL << 31))
+    return fail(S5D_EUNSUPPORTED, "padded row exceeds 2^31 bytes");
+
   s5d_tuning req;
   std::memset(&req, 0, sizeof(req));
   if (tuning) {
@@ -237,6 +250,10 @@ s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_p
     cpl = req.tile0 / 64;
   }
   int bt = req.bt;
+  if (cpl == 0 && (bt == 0 || bt == default_bt(d.dtype, box, r))) {
+    const int c = default_tuning(d.dtype, box, r).cpl;
+    if (max_bt2d(d.dtype, box, r, c) >= default_bt(d.dtype, box, r)) cpl = c;
+  }
   if (cpl == 0) {
     // widest tile that still reaches the requested (or default) depth
     const int want = bt > 0 ? bt : default_bt(d.dtype, box, r);

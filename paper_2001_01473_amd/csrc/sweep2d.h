@@ -2,7 +2,7 @@
 //
 // Method (AN5D "Execution Model" and "Optimizations"): a tile of the plane
 // normal to the streaming axis (axis 0) walks along axis 0 and carries BT
-// computational streams, one per fused time level.  Level T updates the row
+// computational streams, one per fused time level.  Level T emits the row
 // that lies T*R rows behind the row just loaded, so each row is read from HBM
 // once and written once per BT time steps.  The tile overlaps its neighbours
 // by BT*R columns on each side; the valid width shrinks by 2R per level and
@@ -17,17 +17,31 @@
 //    shifts (wave_shr:1 / wave_shl:1).  Lanes at the tile edge receive
 //    meaningless values, which only ever reach the overlap region that the
 //    shrinking valid width discards.
-//  * per level a window of 2R+1 rows lives in VGPRs with fixed roles ("Register
-//    Allocation"): the stream loop is unrolled by a multiple of 2R+1 so every
-//    window slot is a compile-time register and no value is ever shifted.
-//  * star stencils exchange only the centre row across lanes ("diagonal-access
-//    free"); box stencils exchange each row once when it enters the window and
-//    keep the 2R neighbour values beside it.
-//  * rows are prefetched PF = (2R+1)*PFK steps ahead into staging registers
-//    (PFK = 0 loads each row in place, for stencils whose window is large).
-//  * boundary cells (the fixed halo of width R) are passed through unchanged at
-//    every level ("halo overwrite" in the paper); only waves whose tile or stream
-//    block touches the boundary run that code path.
+//  * partial sums ("associative" stencils in the paper): a row arriving at
+//    level T is pushed at once into the 2R+1 output rows it contributes to,
+//    so a level holds only 2R pending accumulator rows and the arriving row is
+//    dead after its pushes.  Output row o receives its contributions in the
+//    order its source rows arrive, o-R first, so each output is summed in the
+//    canonical offset order: (d0, d1) lexicographic, d0 outermost.  The
+//    accumulator slot of row o is o mod 2R; the stream loop is unrolled by a
+//    multiple of 2R, so every slot is a fixed register ("Register Allocation":
+//    no value is ever shifted between registers).
+//  * loaded rows sit in a ring of NR register rows (one vector register tuple
+//    each; the stream loop is unrolled by lcm(2R, NR)); at step s the slot
+//    consumed at step s-1 receives row s+NR-1, so NR-1 rows are in flight.  The first unrolled iteration is peeled so the
+//    loop is entered with the same loads and stores outstanding as at its back
+//    edge, which lets the compiler wait on exactly the oldest ring row.
+//  * fixed boundary (width R on every face): cells of the boundary keep their
+//    value at every level (the paper overwrites them with the original value).
+//    Only waves whose tile or stream block touches the boundary (EDGE) do this:
+//    boundary rows are re-read from the source buffer (never written, and
+//    L2-resident since level 0 has just read them); the boundary-column cells
+//    of the last BT*R+1 rows are stashed in LDS when level 0 loads them.  EDGE waves read through buffer descriptors, so columns and rows
+//    outside the grid read as 0 without a branch; interior waves read whole
+//    lane vectors.  Stores go through per-row buffer descriptors: lanes whose
+//    cells all lie in the compute region store one vector, the lanes at its
+//    edge store cell by cell, and out-of-range offsets turn the unused path
+//    and the masked cells into no-ops without a branch.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -37,6 +51,10 @@
 #include <utility>
 
 #include "s5d_internal.h"
+
+// Every lambda of the kernel bodies must be inlined: their arrays are register
+// state and only become registers (not scratch memory) once inlined.
+#define S5D_INL __attribute__((always_inline))
 
 namespace s5d {
 
@@ -54,17 +72,19 @@ __device__ __forceinline__ void sfor(F&& f) {
 }
 
 constexpr int pmod(int a, int m) { return ((a % m) + m) % m; }
+constexpr int gcd_i(int a, int b) { return b == 0 ? a : gcd_i(b, a % b); }
+constexpr int lcm_i(int a, int b) { return a / gcd_i(a, b) * b; }
 
 // DPP whole-wavefront shifts by one lane.  wave_shr:1 (0x138) hands lane l
 // the value of lane l-1; wave_shl:1 (0x130) hands lane l the value of lane
-// l+1.  The lane without a source receives 0.
+// l+1.  bound_ctrl makes the lane without a source read 0, so no old value
+// has to be materialised.
 __device__ __forceinline__ int lane_from_lower_i32(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true);
 }
 __device__ __forceinline__ int lane_from_upper_i32(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true);
 }
-
 __device__ __forceinline__ float lane_from_lower(float v) {
   return __int_as_float(lane_from_lower_i32(__float_as_int(v)));
 }
@@ -75,19 +95,60 @@ __device__ __forceinline__ double lane_from_lower(double v) {
   const long long b = __double_as_longlong(v);
   const int lo = lane_from_lower_i32(static_cast<int>(b));
   const int hi = lane_from_lower_i32(static_cast<int>(b >> 32));
-  return __longlong_as_double((static_cast<long long>(hi) << 32) |
-                              static_cast<unsigned int>(lo));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 __device__ __forceinline__ double lane_from_upper(double v) {
   const long long b = __double_as_longlong(v);
   const int lo = lane_from_upper_i32(static_cast<int>(b));
   const int hi = lane_from_upper_i32(static_cast<int>(b >> 32));
-  return __longlong_as_double((static_cast<long long>(hi) << 32) |
-                              static_cast<unsigned int>(lo));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Buffer descriptors (gfx9 family: 3rd dword 0x00020000, raw byte
+// addressing).  An access whose byte offset is >= nbytes reads 0 / is dropped.
+constexpr uint32_t kOutOfRange = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), static_cast<short>(0),
+                                           static_cast<int>(nbytes), 0x00020000);
+}
+__device__ __forceinline__ void buf_load(float& v, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  v = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, static_cast<int>(off), 0, 0));
+}
+__device__ __forceinline__ void buf_load(double& v, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, static_cast<int>(off), 0, 0));
+}
+__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, static_cast<int>(off), 0, 0);
+}
+__device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  using u2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(rs, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, static_cast<int>(off), 0, 0);
+}
+// A lane's CPL consecutive cells as 16-byte stores (CPL*sizeof(T) is a
+// multiple of 16); an out-of-range offset drops the whole vector.
+template <typename T, int CPL>
+__device__ __forceinline__ void buf_store_lane(const T (&v)[CPL], __amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  static_assert((CPL * sizeof(T)) % 16 == 0, "lane vector must be whole 16-byte pieces");
+  using u4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(rs, 0, 0, 0));
+  constexpr int PER = 16 / sizeof(T);
+#pragma unroll
+  for (int q = 0; q < CPL / PER; ++q) {
+    T piece[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) piece[j] = v[q * PER + j];
+    const uint32_t o = off == kOutOfRange ? kOutOfRange : off + q * 16u;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, piece), rs, static_cast<int>(o), 0, 0);
+  }
+}
+
+// A lane's CPL consecutive cells, element-aligned, read as one vector access.
+template <typename T, int N>
+struct __attribute__((packed, aligned(sizeof(T)))) LaneVec {
+  T v[N];
+};
 
 // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so
 // that consecutive logical blocks (neighbouring tiles, which share BT*R
@@ -97,15 +158,24 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nblk) {
   return x < rem ? x * (q + 1) + i : rem * (q + 1) + (x - rem) * q + i;
 }
 
-template <typename T, int R, bool BOX, int BT, int CPL, int PFK, bool EDGE>
+// Per-wave LDS stash of the boundary-column cells of the last BT*R+1 rows,
+// used by EDGE waves only: lane vectors of the (at most 4) lanes that hold
+// boundary columns.
+template <typename T, int R, int BT, int CPL>
+struct alignas(16) EdgeStash {
+  T cols[BT * R + 1][4][CPL];
+};
+
+template <typename T, int R, bool BOX, int BT, int CPL, int NR, bool EDGE>
 __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPack<T, npts(2, R, BOX)>& cf,
-                                             int lane, int tile, int chunk) {
-  constexpr int U = 2 * R + 1;        // window rows per level
-  constexpr int W = 64 * CPL;         // tile width (columns)
-  constexpr int C = W - 2 * BT * R;   // compute-region width
-  constexpr int PF = U * PFK;         // prefetch distance in steps (0: load in place)
-  constexpr int NS = PF > 0 ? PF : U; // steps per unrolled iteration
-  constexpr int NX = BOX ? 2 * R : 1; // cached lane-exchange values per window row
+                                             int lane, int tile, int chunk, EdgeStash<T, R, BT, CPL>* stash) {
+  constexpr int NA = 2 * R;         // pending output rows per level
+  constexpr int NS = lcm_i(NA, NR); // steps per unrolled iteration (NR: rows in the load ring)
+  constexpr int W = 64 * CPL;       // tile width (columns)
+  constexpr int C = W - 2 * BT * R; // compute-region width
+  constexpr int MCOL = BT * R + 1;  // rows kept in the boundary-column stash
+  constexpr int XL = CPL + 2 * R;   // extended row: R cells of lane-1 | own CPL | R cells of lane+1
+  constexpr uint32_t WB = sizeof(T);
 
   const int I0 = a.I0, I1 = a.I1;
   const int P0 = I0 + 2 * R, P1 = I1 + 2 * R;
@@ -113,156 +183,181 @@ __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPac
   const int col0 = c_first - BT * R;     // first column of the tile
   const int row_a = R + chunk * a.chunk; // first output row of this stream block
   const int row_b = min(row_a + a.chunk, I0 + R);
+  const int colL = col0 + lane * CPL;    // first column owned by this lane
 
-  int ldcol[CPL];
-  bool st[CPL], hcol[CPL];
-#pragma unroll
-  for (int k = 0; k < CPL; ++k) {
-    const int col = col0 + lane * CPL + k;
-    ldcol[k] = min(max(col, 0), P1 - 1);
-    st[k] = col >= c_first && col < c_first + C && col < I1 + R;
-    hcol[k] = col < R || col >= I1 + R;
+  // Stores: a lane whose CPL cells all lie in the compute region writes them
+  // as one vector (vstore); the few lanes that straddle its edge write cell by
+  // cell (soff).  Out-of-range offsets make the other path a no-op.
+  uint32_t soff[CPL];
+  bool full = true;
+  sfor<CPL>([&](auto K) S5D_INL {
+    const int col = colL + K;
+    const bool st = col >= c_first && col < c_first + C && col < I1 + R;
+    full = full && st;
+    soff[K] = st ? static_cast<uint32_t>(col) * WB : kOutOfRange;
+  });
+  const uint32_t vstore = full ? static_cast<uint32_t>(colL) * WB : kOutOfRange;
+  if (full) sfor<CPL>([&](auto K) S5D_INL { soff[K] = kOutOfRange; });
+  uint32_t loff[CPL];
+  bool hcol[CPL];
+  int hl = -1;  // index of this lane in the boundary-column stash
+  if constexpr (EDGE) {
+    bool left = false, right = false;
+    sfor<CPL>([&](auto K) S5D_INL {
+      const int col = colL + K;
+      loff[K] = (col >= 0 && col < P1) ? static_cast<uint32_t>(col) * WB : kOutOfRange;
+      const bool l = col >= 0 && col < R, r = col >= I1 + R && col < P1;
+      hcol[K] = l || r;
+      left |= l;
+      right |= r;
+    });
+    const int lL = (0 - col0) / CPL;       // lane holding column 0 (col0 <= 0 when present)
+    const int lR = (I1 + R - col0) / CPL;  // lane holding column I1+R
+    if (left) hl = lane - lL;
+    else if (right) hl = 2 + lane - lR;
   }
 
   const T* __restrict__ src = static_cast<const T*>(a.src);
   T* __restrict__ dst = static_cast<T*>(a.dst);
 
-  T win[BT][U][CPL];
-  T ext[BT][U][NX];
-  T stage[PF > 0 ? PF : 1][CPL];
-  sfor<BT>([&](auto L) {
-    sfor<U>([&](auto S) {
-      sfor<CPL>([&](auto K) { win[L][S][K] = T(0); });
-      sfor<NX>([&](auto K) { ext[L][S][K] = T(0); });
-    });
-  });
-
-  auto load_row = [&](T (&v)[CPL], int row) {
-    const T* rp = src + static_cast<int64_t>(min(row, P0 - 1)) * P1;
-    sfor<CPL>([&](auto K) { v[K] = rp[ldcol[K]]; });
-  };
-  // Neighbour values of a row held by the adjacent lanes: x[0..R-1] are the
-  // last R cells of lane l-1, x[R..2R-1] the first R cells of lane l+1.
-  auto exchange = [&](const T (&v)[CPL], T (&x)[NX]) {
-    if constexpr (BOX) {
-      sfor<R>([&](auto J) {
-        x[J] = lane_from_lower(v[CPL - R + J]);
-        x[R + J] = lane_from_upper(v[J]);
-      });
+  auto load_row = [&](T (&v)[CPL], int row) S5D_INL {
+    if constexpr (EDGE) {
+      const auto rs = make_rsrc(src + static_cast<int64_t>(min(row, P0)) * P1,
+                                row < P0 ? static_cast<uint32_t>(P1) * WB : 0u);
+      sfor<CPL>([&](auto K) S5D_INL { buf_load(v[K], rs, loff[K]); });
+    } else {
+      const T* rp = src + static_cast<int64_t>(min(row, P0 - 1)) * P1 + colL;
+      const LaneVec<T, CPL> lv = *reinterpret_cast<const LaneVec<T, CPL>*>(rp);
+      sfor<CPL>([&](auto K) S5D_INL { v[K] = lv.v[K]; });
     }
   };
 
+  T acc[BT][NA][CPL];
+  using RowV = T __attribute__((ext_vector_type(CPL)));
+  RowV ringv[NR];
+  sfor<BT>([&](auto L) S5D_INL { sfor<NA>([&](auto S) S5D_INL { sfor<CPL>([&](auto K) S5D_INL { acc[L][S][K] = T(0); }); }); });
+
   const int s_lo = max(0, row_a - BT * R);
-  const int s0 = s_lo - s_lo % U;       // step phases line up with window slots
-  const int s_end = row_b + BT * R;     // level BT stores row row_b-1 at step s_end-1
+  const int s0 = s_lo - s_lo % NS;    // step phases line up with accumulator slots
+  const int s_end = row_b + BT * R;   // level BT emits row row_b-1 at step s_end-1
   const int niter = (s_end - s0 + NS - 1) / NS;
 
-  if constexpr (PF > 0) sfor<PF>([&](auto J) { load_row(stage[J], s0 + J); });
+  auto load_vec = [&](RowV& v, int row) S5D_INL {
+    T t[CPL];
+    load_row(t, row);
+    sfor<CPL>([&](auto K) S5D_INL { v[+K] = t[K]; });
+  };
+  sfor<NR - 1>([&](auto J) S5D_INL {
+    load_vec(ringv[J], s0 + J);
+    __builtin_amdgcn_sched_barrier(0);  // keep ring order: the loop waits on the oldest load
+  });
 
-  for (int it = 0; it < niter; ++it) {
-    const int sb = s0 + it * NS;
-    sfor<NS>([&](auto PH) {
-      constexpr int ph = PH;
-      const int s = sb + ph;
-      constexpr int sl0 = ph % U;
-      if constexpr (PF > 0) {
-        sfor<CPL>([&](auto K) { win[0][sl0][K] = stage[ph][K]; });
-        load_row(stage[ph], s + PF);
-      } else {
-        load_row(win[0][sl0], s);
+  auto iteration = [&](const int sb) S5D_INL {
+    sfor<NS>([&](auto PH) S5D_INL {
+      const int s = sb + PH;
+      // the slot consumed at the previous step is free: request row s+NR-1 into it
+      load_vec(ringv[pmod(PH - 1, NR)], s + NR - 1);
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (EDGE) {
+        // level 0 holds original values: stash the boundary columns of row s
+        if (hl >= 0) sfor<CPL>([&](auto K) S5D_INL { stash->cols[s % MCOL][hl][K] = ringv[PH % NR][+K]; });
       }
-      exchange(win[0][sl0], ext[0][sl0]);
+      T cur[CPL];
+      sfor<CPL>([&](auto K) S5D_INL { cur[K] = ringv[PH % NR][+K]; });
 
-      sfor<BT>([&](auto LI) {
-        constexpr int lv = LI + 1;            // level computed here
-        constexpr int base = ph - lv * R;     // its output row is s - lv*R
-        const T(&w)[U][CPL] = win[lv - 1];
-        const T(&x)[U][NX] = ext[lv - 1];
-        constexpr int cs = pmod(base, U);     // slot of the centre row
+      sfor<BT>([&](auto LI) S5D_INL {
+        constexpr int lv = LI + 1;                       // level receiving row p = s-(lv-1)*R
+        constexpr int pm = pmod(PH - (lv - 1) * R, NA);  // p mod 2R
+        constexpr int so = pmod(pm + R, NA);             // slot of rows p-R and p+R
+        T(&A)[NA][CPL] = acc[LI];
+
+        T E[XL];
+        sfor<CPL>([&](auto K) S5D_INL { E[R + K] = cur[K]; });
+        sfor<R>([&](auto J) S5D_INL {
+          E[J] = lane_from_lower(cur[CPL - R + J]);
+          E[R + CPL + J] = lane_from_upper(cur[J]);
+        });
+
+        // contribution of the arriving row to the output d0 rows before it
+        auto add_row = [&](auto D0, T& acc_k, auto K, auto FIRST) S5D_INL {
+          constexpr int d0 = D0;
+          constexpr bool first = FIRST;
+          if constexpr (BOX) {
+            sfor<2 * R + 1>([&](auto D1) S5D_INL {
+              constexpr int ci = (d0 + R) * (2 * R + 1) + D1;
+              if constexpr (first && D1 == 0) acc_k = cf.c[ci] * E[K + D1];
+              else acc_k = fmadd(cf.c[ci], E[K + D1], acc_k);
+            });
+          } else if constexpr (d0 != 0) {
+            constexpr int ci = d0 < 0 ? d0 + R : 3 * R + d0;
+            if constexpr (first) acc_k = cf.c[ci] * cur[K];
+            else acc_k = fmadd(cf.c[ci], cur[K], acc_k);
+          } else {
+            sfor<2 * R + 1>([&](auto D1) S5D_INL { acc_k = fmadd(cf.c[R + D1], E[K + D1], acc_k); });
+          }
+        };
+
+        // 1. output p-R receives its last contribution (d0 = +R) and leaves
         T out[CPL];
+        sfor<CPL>([&](auto K) S5D_INL {
+          T v = A[so][K];
+          add_row(ic<R>{}, v, K, std::false_type{});
+          out[K] = v;
+        });
+        // 2. output p+R starts in the freed slot (d0 = -R)
+        sfor<CPL>([&](auto K) S5D_INL { add_row(ic<-R>{}, A[so][K], K, std::true_type{}); });
+        // 3. outputs p+R-1 .. p-R+1 (d0 = -R+1 .. R-1)
+        sfor<2 * R - 1>([&](auto J) S5D_INL {
+          constexpr int d0 = -R + 1 + J;
+          constexpr int sl = pmod(pm - d0, NA);
+          sfor<CPL>([&](auto K) S5D_INL { add_row(ic<d0>{}, A[sl][K], K, std::false_type{}); });
+        });
 
-        if constexpr (!BOX) {
-          // centre row extended by R cells of each neighbouring lane
-          T E[CPL + 2 * R];
-          sfor<R>([&](auto J) {
-            E[J] = lane_from_lower(w[cs][CPL - R + J]);
-            E[R + CPL + J] = lane_from_upper(w[cs][J]);
-          });
-          sfor<CPL>([&](auto K) { E[R + K] = w[cs][K]; });
-          sfor<CPL>([&](auto K) {
-            // canonical order: (-R,0)..(-1,0), (0,-R)..(0,R), (1,0)..(R,0)
-            T acc = cf.c[0] * w[pmod(base - R, U)][K];
-            sfor<R - 1>([&](auto D) {
-              acc = fmadd(cf.c[1 + D], w[pmod(base - R + 1 + D, U)][K], acc);
-            });
-            sfor<2 * R + 1>([&](auto D) { acc = fmadd(cf.c[R + D], E[K + D], acc); });
-            sfor<R>([&](auto D) {
-              acc = fmadd(cf.c[3 * R + 1 + D], w[pmod(base + 1 + D, U)][K], acc);
-            });
-            out[K] = acc;
-          });
-        } else {
-          // canonical order: d0 = -R..R outer, d1 = -R..R inner
-          sfor<CPL>([&](auto K) {
-            T acc;
-            sfor<2 * R + 1>([&](auto D0) {
-              constexpr int sl = pmod(base - R + D0, U);
-              sfor<2 * R + 1>([&](auto D1) {
-                constexpr int m = K + D1;     // index into [left R | own CPL | right R]
-                T v;
-                if constexpr (m < R) {
-                  v = x[sl][m];
-                } else if constexpr (m < R + CPL) {
-                  v = w[sl][m - R];
-                } else {
-                  v = x[sl][m - CPL];
-                }
-                constexpr int ci = D0 * (2 * R + 1) + D1;
-                if constexpr (ci == 0) {
-                  acc = cf.c[0] * v;
-                } else {
-                  acc = fmadd(cf.c[ci], v, acc);
-                }
-              });
-            });
-            out[K] = acc;
-          });
-        }
 
         if constexpr (EDGE) {
-          // fixed boundary: rows 0..R-1 and I0+R.., columns 0..R-1 and I1+R..
-          const int q = s - lv * R;
-          if (q < R || q >= I0 + R) {
-            sfor<CPL>([&](auto K) { out[K] = w[cs][K]; });
+          const int o = s - lv * R;
+          if (o < R || o >= I0 + R) {
+            // boundary row: never written, so the source buffer still holds it
+            if (o >= 0 && o < P0) load_row(out, o);
           } else {
-            sfor<CPL>([&](auto K) { out[K] = hcol[K] ? w[cs][K] : out[K]; });
+            // every lane reads a stash slot (its own, or slot 0 if it holds no
+            // boundary column, where hcol is all false): no divergent branch
+            const LaneVec<T, CPL> hv = *reinterpret_cast<const LaneVec<T, CPL>*>(
+                stash->cols[o % MCOL][hl < 0 ? 0 : hl]);
+            sfor<CPL>([&](auto K) S5D_INL { out[K] = hcol[K] ? hv.v[K] : out[K]; });
           }
         }
 
         if constexpr (lv < BT) {
-          sfor<CPL>([&](auto K) { win[lv][cs][K] = out[K]; });
-          exchange(win[lv][cs], ext[lv][cs]);
+          sfor<CPL>([&](auto K) S5D_INL { cur[K] = out[K]; });
         } else {
-          const int q = s - BT * R;
-          if (q >= row_a && q < row_b) {
-            T* rp = dst + static_cast<int64_t>(q) * P1;
-            sfor<CPL>([&](auto K) {
-              if (st[K]) rp[ldcol[K]] = out[K];
-            });
-          }
+          // rows outside the stream block get an empty descriptor: no branch,
+          // so the whole unrolled iteration stays one basic block
+          const int o = s - BT * R;
+          const bool keep = o >= row_a && o < row_b;
+          const auto rs = make_rsrc(dst + static_cast<int64_t>(keep ? o : row_a) * P1,
+                                    keep ? static_cast<uint32_t>(P1) * WB : 0u);
+          buf_store_lane(out, rs, vstore);
+          sfor<CPL>([&](auto K) S5D_INL { buf_store(out[K], rs, soff[K]); });
         }
       });
     });
-  }
+  };
+  // The first iteration is peeled so that the loop is entered with the same
+  // memory operations in flight as at its back edge: the wait on the oldest
+  // ring row then counts every younger load and store.
+  iteration(s0);
+  for (int it = 1; it < niter; ++it) iteration(s0 + it * NS);
 }
 
-template <typename T, int R, bool BOX, int BT, int CPL, int PFK>
+template <typename T, int R, bool BOX, int BT, int CPL, int NR>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void sweep2d_kernel(Sweep2DArgs a,
                                                                     CoefPack<T, npts(2, R, BOX)> cf) {
   constexpr int W = 64 * CPL;
   constexpr int C = W - 2 * BT * R;
   static_assert(R <= CPL, "the lane exchange reaches one neighbouring lane only");
   static_assert(C >= 1, "tile narrower than its overlap");
+  __shared__ EdgeStash<T, R, BT, CPL> stash[kWavesPerBlock];
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wid = lb * kWavesPerBlock + wib;
@@ -278,12 +373,12 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void sweep2d_kernel(Sweep2DArg
   const bool edge = col0 < 0 || col0 + W > P1 || row_a - (BT - 1) * R < R ||
                     row_b + (BT - 1) * R > a.I0 + R;
   if (edge)
-    sweep2d_body<T, R, BOX, BT, CPL, PFK, true>(a, cf, lane, tile, chunk);
+    sweep2d_body<T, R, BOX, BT, CPL, NR, true>(a, cf, lane, tile, chunk, &stash[wib]);
   else
-    sweep2d_body<T, R, BOX, BT, CPL, PFK, false>(a, cf, lane, tile, chunk);
+    sweep2d_body<T, R, BOX, BT, CPL, NR, false>(a, cf, lane, tile, chunk, &stash[wib]);
 }
 
-template <typename T, int R, bool BOX, int BT, int CPL, int PFK>
+template <typename T, int R, bool BOX, int BT, int CPL, int NR>
 hipError_t launch_sweep2d(const Round2D& rd) {
   constexpr int NP = npts(2, R, BOX);
   constexpr int C = 64 * CPL - 2 * BT * R;
@@ -300,23 +395,23 @@ hipError_t launch_sweep2d(const Round2D& rd) {
   a.nwaves = a.ntiles * nchunks;
   a.pad = 0;
   const int nblk = (a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
-  hipLaunchKernelGGL((sweep2d_kernel<T, R, BOX, BT, CPL, PFK>), dim3(nblk), dim3(64 * kWavesPerBlock), 0,
+  hipLaunchKernelGGL((sweep2d_kernel<T, R, BOX, BT, CPL, NR>), dim3(nblk), dim3(64 * kWavesPerBlock), 0,
                      rd.stream, a, cf);
   return hipGetLastError();
 }
 
-template <typename T, int R, bool BOX, int BT, int CPL, int PFK>
+template <typename T, int R, bool BOX, int BT, int CPL, int NR>
 int occupancy_sweep2d() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep2d_kernel<T, R, BOX, BT, CPL, PFK>,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep2d_kernel<T, R, BOX, BT, CPL, NR>,
                                                    64 * kWavesPerBlock, 0) != hipSuccess)
     return 0;
   return nb;
 }
 
-template <typename T, int R, bool BOX, int BT, int CPL, int PFK>
+template <typename T, int R, bool BOX, int BT, int CPL, int NR>
 Kernel2D make_kernel2d() {
-  return Kernel2D{&launch_sweep2d<T, R, BOX, BT, CPL, PFK>, &occupancy_sweep2d<T, R, BOX, BT, CPL, PFK>, CPL, BT,
+  return Kernel2D{&launch_sweep2d<T, R, BOX, BT, CPL, NR>, &occupancy_sweep2d<T, R, BOX, BT, CPL, NR>, CPL, BT,
                   64 * CPL};
 }
 

@@ -26,7 +26,7 @@ F64_TOL = 1e-12
 
 
 def _vid(v):
-    dtype, box, r, cpl, bt, pfk = v
+    dtype, box, r, cpl, bt, nr = v
     return "%s-%s%d-c%d-b%d" % ("f32" if dtype == 0 else "f64", "box" if box else "star", r, cpl, bt)
 
 
@@ -34,7 +34,7 @@ def _geometry(v):
     """Interior extents spanning >= 2 tiles plus a ragged tail, and >= 3 stream
     blocks plus a ragged tail; the stream block may be shorter than the
     warm-up (b_T * r rows)."""
-    dtype, box, r, cpl, bt, pfk = v
+    dtype, box, r, cpl, bt, nr = v
     C = 64 * cpl - 2 * bt * r
     I1 = 2 * C + C // 2 + 7
     chunk = 19 + bt
@@ -48,7 +48,7 @@ def _np_dtype(v):
 
 @pytest.mark.parametrize("v", VARIANTS, ids=[_vid(v) for v in VARIANTS])
 def test_variant_dyadic_bitwise(v):
-    dtype, box, r, cpl, bt, pfk = v
+    dtype, box, r, cpl, bt, nr = v
     dt = _np_dtype(v)
     (I0, I1), chunk = _geometry(v)
     bits = 24 if dt == np.float32 else 53
@@ -67,7 +67,7 @@ def test_variant_dyadic_bitwise(v):
 
 @pytest.mark.parametrize("v", VARIANTS, ids=[_vid(v) for v in VARIANTS])
 def test_variant_random_parity(v):
-    dtype, box, r, cpl, bt, pfk = v
+    dtype, box, r, cpl, bt, nr = v
     dt = _np_dtype(v)
     (I0, I1), chunk = _geometry(v)
     T = 2 * bt + 3
@@ -120,9 +120,13 @@ def test_round_parity_and_remainders(T):
 def test_blocking_invariance_f64():
     """b_T, h_SN and cells-per-lane choices give identical bits."""
     case = si.make_case(41, 2, 2, False, (211, 777), 24)
+    built = {(v[3], v[4]) for v in VARIANTS if v[:3] == (1, 0, 2)}
+    wanted = [(1, 4, 64), (2, 2, 17), (3, 4, 500), (4, 4, 9), (6, 2, 33),
+              (8, 2, 250), (10, 2, 40), (4, 2, 211), (5, 4, 31), (7, 2, 12)]
+    configs = [(bt, cpl, ch) for bt, cpl, ch in wanted if (cpl, bt) in built]
+    assert len(configs) >= 6, configs
     outs = []
-    for bt, cpl, chunk in [(1, 4, 64), (2, 2, 17), (3, 4, 500), (4, 4, 9), (6, 2, 33),
-                           (8, 2, 250), (10, 2, 40), (4, 2, 211)]:
+    for bt, cpl, chunk in configs:
         say("invariance", bt, cpl, chunk)
         got, info = run_gpu(case.grid, radius=2, box=False, coeffs=case.coeffs, steps=24,
                             bt=bt, cells_per_lane=cpl, stream_chunk=chunk)
