@@ -84,6 +84,8 @@ class Problem:
         rng = np.random.default_rng(seed)
         c = si.random_coeffs(rng, npts(r, box))
         self.coeffs = c
+        c = si.random_coeffs(rng, si.n_points(len(interior), r, box))
+        self.coeffs = c
         shape = si.padded_shape(interior, r)
         td = torch.float32 if dtype == "f32" else torch.float64
         gen = torch.Generator(device="cuda:0").manual_seed(seed)
@@ -92,10 +94,10 @@ class Problem:
         self.buf0 = torch.rand(shape, dtype=td, device="cuda:0", generator=gen)
         self.buf1 = torch.empty_like(self.buf0)
         self.init = self.buf0.clone()
-        self.plan = s5d.Plan(ndim=2, radius=r, box=box, dtype=dtype, interior=interior,
+        self.plan = s5d.Plan(ndim=len(interior), radius=r, box=box, dtype=dtype, interior=interior,
                              steps=steps, coeffs=c, **tuning)
         self.info = self.plan.query()
-        self.cells = interior[0] * interior[1]
+        self.cells = int(np.prod(interior))
 
     def reset(self):
         self.buf0.copy_(self.init)
@@ -204,6 +206,31 @@ def cpu_baseline(r, box, dtype, target_s=12.0):
             "cores": oracle.max_threads(), "kind": "oracle",
             "sample": "%s %s %dx%d interior, %d steps (of %d), %.1f s" % (
                 stencil_name(r, box), dtype, N, N, steps, T_STEPS, dt)}
+
+
+N3 = 512
+
+
+def full_sweep3d():
+    """Every compiled 3D variant at 512^3, T = 1000 (one warm-up, one timed run)."""
+    import torch
+    from paper_2001_01473_amd import build as lib_build
+    for dtype_code, box, r, cpl, m, nw, bt, nr in lib_build.variants_3d():
+        dtype = "f32" if dtype_code == 0 else "f64"
+        name = "%s3d%dr" % ("box" if box else "star", r)
+        try:
+            p = Problem(r, bool(box), dtype, interior=(N3, N3, N3), bt=bt, cells_per_lane=cpl,
+                        rows_per_wave=m)
+        except Exception as e:  # noqa: BLE001 - reported, not fatal
+            print(json.dumps({"stencil": name, "dtype": dtype, "bt": bt, "tile": [nw * m, 64 * cpl],
+                              "error": str(e)[:120]}), flush=True)
+            continue
+        s = time_steps(p, 1, 1)
+        g = N3 ** 3 * T_STEPS / s / 1e9
+        print(json.dumps({"stencil": name, "dtype": dtype, "bt": bt, "tile": [nw * m, 64 * cpl],
+                          "stream_chunk": p.info["stream_chunk"], "gcells": round(g, 1)}), flush=True)
+        p.close()
+        torch.cuda.empty_cache()
 
 
 def full_sweep():
@@ -316,6 +343,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--bt", type=int, default=0, help="force b_T for the headline run")
     ap.add_argument("--probe", action="store_true")
+    ap.add_argument("--full-sweep3d", action="store_true",
+                    help="time every compiled 3D variant at 512^3, T = 1000")
     ap.add_argument("--full-sweep", action="store_true",
                     help="time every compiled (stencil, dtype, b_T, cells per lane) at the "
                          "benchmark size and print one JSON line per variant")
@@ -343,6 +372,9 @@ def main(argv=None):
         return 0
     if args.full_sweep:
         full_sweep()
+        return 0
+    if args.full_sweep3d:
+        full_sweep3d()
         return 0
 
     tuning = {"bt": args.bt} if args.bt else {}

@@ -88,10 +88,11 @@ typedef struct s5d_desc {
 typedef struct s5d_tuning {
     uint32_t struct_size;
     int32_t bt;             /* temporal blocking degree b_T: time steps fused per launch */
-    int32_t tile0;          /* b_S along axis 1 (cells, overlap included) */
-    int32_t tile1;          /* b_S along axis 2 (3D only) */
+    int32_t tile0;          /* 2D: b_S along axis 1; 3D: b_S along axis 1 (rows) */
+    int32_t tile1;          /* 3D: b_S along axis 2 (columns); 2D: unused */
     int32_t stream_chunk;   /* h_SN: axis-0 length of one stream block */
-    int32_t cells_per_lane; /* consecutive axis-last cells owned by one lane */
+    int32_t cells_per_lane; /* consecutive cells of the last axis owned by one lane */
+    int32_t rows_per_wave;  /* 3D: consecutive axis-1 rows held by one wave */
     int32_t waves_per_eu;   /* reserved, 0 */
 } s5d_tuning;
 
@@ -129,6 +130,33 @@ s5d_status s5d_plan_query(const s5d_plan *plan, s5d_tuning *chosen, int64_t *byt
  * except launch failures (S5D_EDEVICE), which may leave a partial sweep. */
 s5d_status s5d_run(const s5d_plan *plan, void *buf0, void *buf1, void *stream,
                    int32_t *result_index);
+
+/* Error and norm reductions in float64 between a computed grid and a
+ * reference, for checking a sweep against an independent result on the GPU
+ * (the relative error measure of the accuracy evaluation).  Over the n
+ * elements g = got[i], o = ref[i], with d = |g - o| formed in float64, `out`
+ * receives S5D_NORMS_COUNT doubles:
+ *   out[0] = max d,   out[1] = max |o|,
+ *   out[2] = max (d / |o|), taking d itself where o = 0,
+ *   out[3] = sqrt(sum d^2 / n),   out[4] = sqrt(sum o^2 / n).
+ * A NaN in g or o propagates into out[0], out[2] and out[3].  n = 0 gives zeros.
+ *   got, ref: device pointers, n elements of got_dtype / ref_dtype (S5D_F32 or
+ *             S5D_F64), 16-byte aligned (any torch allocation is).
+ *   out: device pointer, S5D_NORMS_COUNT doubles, 8-byte aligned; every value
+ *        is written, so it needs no clearing.
+ *   workspace: device memory of at least s5d_error_norms_workspace_bytes(n)
+ *        bytes (at most 80 KiB), not overlapping out; the caller owns it and
+ *        must not reuse it before the stream has passed this call.
+ * Asynchronous on `stream` (a hipStream_t; NULL = null stream); two kernel
+ * launches, no allocation and no host synchronisation, so the call may be
+ * captured in a HIP graph.  The result is a deterministic function of the
+ * inputs and n.  Errors: S5D_EINVAL before anything is enqueued,
+ * S5D_EDEVICE if a launch fails. */
+#define S5D_NORMS_COUNT 5
+int64_t s5d_error_norms_workspace_bytes(int64_t n); /* -1 if n < 0 */
+s5d_status s5d_error_norms(const void *got, int32_t got_dtype, const void *ref, int32_t ref_dtype,
+                           int64_t n, double *out, void *workspace, int64_t workspace_bytes,
+                           void *stream);
 
 /* Human-readable name of a status code (static storage). */
 const char *s5d_status_string(s5d_status status);

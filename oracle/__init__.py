@@ -12,7 +12,9 @@ with gcc when it is missing, and marshals numpy arrays.
 
 Every function here is pinned by ``tests/test_oracle_pins.py`` against exact
 dyadic arithmetic, exact rational brute force, closed-form eigenmodes,
-scipy's correlate/convolve and structural invariants.
+scipy's correlate/convolve and structural invariants; the compensated float32
+variant against exact rational sums and the published error bound of the
+compensated dot product.
 """
 from __future__ import annotations
 
@@ -39,7 +41,7 @@ def build(force: bool = True) -> str:
     """Compile ``oracle.c`` into ``liboracle.so`` next to it; returns its path."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.run(["gcc", *CFLAGS, _SRC, "-o", tmp], check=True)
+        subprocess.run(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"], check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -55,7 +57,7 @@ def _load():
             lib.oracle_offsets.restype = ctypes.c_int
             lib.oracle_offsets.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_void_p]
-            for name in ("oracle_sweep_f64", "oracle_sweep_f32"):
+            for name in ("oracle_sweep_f64", "oracle_sweep_f32", "oracle_sweep_f32_dot2"):
                 fn = getattr(lib, name)
                 fn.restype = ctypes.c_int
                 fn.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, i64p,
@@ -83,16 +85,24 @@ def max_threads() -> int:
 
 
 def sweep(a0: np.ndarray, *, radius: int, box: bool, coeffs, steps: int,
-          threads: int = 0) -> np.ndarray:
+          threads: int = 0, accum: str = "plain") -> np.ndarray:
     """Run T = ``steps`` steps of the naive double-buffered loop.
 
     ``a0`` is the padded initial grid (boundary included), float64 or float32;
     the working precision is ``a0.dtype`` and ``coeffs`` are cast to it.
+    ``accum="compensated"`` (float32 only) sums each cell's terms with the
+    compensated dot product (Dot2) instead of plain left-to-right addition.
     Returns a new array holding A[T % 2] (the input is not modified).
     ``threads`` = 0 keeps OpenMP's default.
     """
     a0 = np.asarray(a0)
-    if a0.dtype == np.float64:
+    if accum not in ("plain", "compensated"):
+        raise ValueError("accum must be 'plain' or 'compensated'")
+    if accum == "compensated":
+        if a0.dtype != np.float32:
+            raise TypeError("compensated accumulation is defined for float32 grids")
+        fn, ct = _load().oracle_sweep_f32_dot2, np.float32
+    elif a0.dtype == np.float64:
         fn, ct = _load().oracle_sweep_f64, np.float64
     elif a0.dtype == np.float32:
         fn, ct = _load().oracle_sweep_f32, np.float32

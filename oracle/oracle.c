@@ -121,6 +121,74 @@ int oracle_offsets(int ndim, int radius, int box, int32_t *out)
 ORACLE_SWEEP(oracle_sweep_f64, double)
 ORACLE_SWEEP(oracle_sweep_f32, float)
 
+/*
+ * Compensated float32 accumulation (the float32 "Kahan" variant of the
+ * library): each cell's terms are summed with the compensated dot product of
+ * Ogita, Rump and Oishi (SIAM J. Sci. Comput. 26(6), 2005, Dot2): every
+ * product c*x is split exactly into its rounded value h and error e by a
+ * fused multiply-add, h is added to the running sum s with the error-free
+ * two-sum of Knuth (s' = s + h, error t), the errors are gathered in a second
+ * float32 accumulator q = q + (e + t), and the cell receives s + q rounded
+ * once.  The first term sets s = h, q = e.  Same canonical term order as the
+ * plain sweep.
+ */
+#include <math.h>
+
+static float dot2_cell(const float *coeffs, const float *src, int64_t p, const int64_t *lin, int n)
+{
+    float h = coeffs[0] * src[p + lin[0]];
+    float s = h;
+    float q = fmaf(coeffs[0], src[p + lin[0]], -h);
+    for (int k = 1; k < n; ++k) {
+        float x = src[p + lin[k]];
+        h = coeffs[k] * x;
+        float e = fmaf(coeffs[k], x, -h);
+        float t1 = s + h;
+        float z = t1 - s;
+        float t = (s - (t1 - z)) + (h - z);
+        s = t1;
+        q = q + (e + t);
+    }
+    return s + q;
+}
+
+int oracle_sweep_f32_dot2(int ndim, int radius, int box, const int64_t *interior, int64_t steps,
+                          const float *coeffs, int64_t n_coeffs, float *buf0, float *buf1,
+                          int threads)
+{
+    int32_t off3[3 * ORACLE_MAX_POINTS];
+    int n = oracle_offsets(ndim, radius, box, off3);
+    if (n < 0 || n != n_coeffs || steps < 0 || !buf0 || !buf1 || !coeffs)
+        return -1;
+    int64_t I0 = interior[0], I1 = interior[1];
+    int64_t I2 = (ndim == 3) ? interior[2] : 1;
+    if (I0 < 1 || I1 < 1 || I2 < 1)
+        return -1;
+    int64_t r = radius;
+    int64_t P0 = I0 + 2 * r, P1 = I1 + 2 * r;
+    int64_t P2 = (ndim == 3) ? I2 + 2 * r : 1;
+    int64_t r2 = (ndim == 3) ? r : 0;
+    int64_t lin[ORACLE_MAX_POINTS];
+    for (int k = 0; k < n; ++k)
+        lin[k] = (int64_t)off3[3 * k] * P1 * P2 + (int64_t)off3[3 * k + 1] * P2 + (int64_t)off3[3 * k + 2];
+    memcpy(buf1, buf0, (size_t)(P0 * P1 * P2) * sizeof(float));
+    if (threads > 0) {
+        OMP_SET(threads);
+    }
+    for (int64_t t = 0; t < steps; ++t) {
+        const float *src = (t % 2 == 0) ? buf0 : buf1;
+        float *dst = (t % 2 == 0) ? buf1 : buf0;
+        OMP_FOR
+        for (int64_t i0 = r; i0 < r + I0; ++i0)
+            for (int64_t i1 = r; i1 < r + I1; ++i1)
+                for (int64_t i2 = r2; i2 < r2 + I2; ++i2) {
+                    int64_t p = (i0 * P1 + i1) * P2 + i2;
+                    dst[p] = dot2_cell(coeffs, src, p, lin, n);
+                }
+    }
+    return (int)(steps % 2);
+}
+
 /* Number of OpenMP threads a parallel region would use (1 without OpenMP). */
 int oracle_max_threads(void)
 {

@@ -16,10 +16,12 @@ from . import _lib
 from ._lib import (ACC_COMPENSATED, ACC_PLAIN, BOX, F32, F64, STAR, Stencil5DError,
                    last_error, status_string)
 
-__all__ = ["Plan", "solve", "Stencil5DError", "status_string", "last_error",
+__all__ = ["Plan", "solve", "error_norms", "NORM_NAMES", "Stencil5DError", "status_string",
+           "last_error",
            "STAR", "BOX", "F32", "F64", "ACC_PLAIN", "ACC_COMPENSATED"]
 
-_TUNING_KEYS = ("bt", "tile0", "tile1", "stream_chunk", "cells_per_lane", "waves_per_eu")
+_TUNING_KEYS = ("bt", "tile0", "tile1", "stream_chunk", "cells_per_lane", "rows_per_wave",
+                "waves_per_eu")
 
 
 def _dtype_code(dtype):
@@ -128,3 +130,38 @@ def solve(grid, *, radius, box, coeffs, steps, accum="plain", stream=None, **tun
     idx = plan.run(grid, other, stream=stream)
     plan.close()
     return grid if idx == 0 else other
+
+
+# Order of the values s5d_error_norms writes.
+NORM_NAMES = ("max_abs_err", "max_abs_ref", "max_rel_err", "rms_err", "rms_ref")
+
+
+def error_norms(got, ref, *, stream=None, out=None, workspace=None):
+    """Float64 error norms of device tensor ``got`` against device tensor
+    ``ref`` (same number of elements, float32 or float64), computed on the GPU
+    by ``s5d_error_norms``.  Returns a float64 device tensor of the five values
+    in NORM_NAMES order (``out`` if given); ``workspace`` (a device tensor of at
+    least ``s5d_error_norms_workspace_bytes`` bytes) is allocated if omitted."""
+    import torch
+    lib = _lib.load()
+    for t in (got, ref):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("got and ref must be contiguous device tensors")
+    n = got.numel()
+    if ref.numel() != n:
+        raise ValueError("got and ref differ in size")
+    need = int(lib.s5d_error_norms_workspace_bytes(n))
+    if out is None:
+        out = torch.empty(_lib.NORMS_COUNT, dtype=torch.float64, device=got.device)
+    if workspace is None:
+        workspace = torch.empty(max(need, 8), dtype=torch.uint8, device=got.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(got.device)
+    handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    _lib.check(lib.s5d_error_norms(ctypes.c_void_p(got.data_ptr()), _dtype_code(got.dtype),
+                                   ctypes.c_void_p(ref.data_ptr()), _dtype_code(ref.dtype),
+                                   int(n), ctypes.c_void_p(out.data_ptr()),
+                                   ctypes.c_void_p(workspace.data_ptr()),
+                                   int(workspace.numel() * workspace.element_size()),
+                                   ctypes.c_void_p(handle)), "s5d_error_norms")
+    return out

@@ -24,7 +24,9 @@ ACC_PLAIN, ACC_COMPENSATED = 0, 1
 
 # Every symbol include/stencil5d.h declares.
 EXPORTS = ("s5d_plan_create", "s5d_plan_destroy", "s5d_plan_query", "s5d_run",
+           "s5d_error_norms_workspace_bytes", "s5d_error_norms",
            "s5d_status_string", "s5d_last_error")
+NORMS_COUNT = 5
 
 
 class S5DDesc(ctypes.Structure):
@@ -39,7 +41,7 @@ class S5DTuning(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("bt", ctypes.c_int32),
                 ("tile0", ctypes.c_int32), ("tile1", ctypes.c_int32),
                 ("stream_chunk", ctypes.c_int32), ("cells_per_lane", ctypes.c_int32),
-                ("waves_per_eu", ctypes.c_int32)]
+                ("rows_per_wave", ctypes.c_int32), ("waves_per_eu", ctypes.c_int32)]
 
 
 class Stencil5DError(RuntimeError):
@@ -73,6 +75,11 @@ def load():
                                        ctypes.POINTER(ctypes.c_int64)]
         lib.s5d_run.restype = ctypes.c_int32
         lib.s5d_run.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int32)]
+        lib.s5d_error_norms_workspace_bytes.restype = ctypes.c_int64
+        lib.s5d_error_norms_workspace_bytes.argtypes = [ctypes.c_int64]
+        lib.s5d_error_norms.restype = ctypes.c_int32
+        lib.s5d_error_norms.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_int64,
+                                        vp, vp, ctypes.c_int64, vp]
         lib.s5d_status_string.restype = ctypes.c_char_p
         lib.s5d_status_string.argtypes = [ctypes.c_int32]
         lib.s5d_last_error.restype = ctypes.c_char_p
@@ -112,9 +119,11 @@ def make_desc(ndim, radius, box, dtype, accum, interior, steps, coeffs):
     return d, c  # keep c alive while d is used
 
 
-def make_tuning(bt=0, tile0=0, tile1=0, stream_chunk=0, cells_per_lane=0, waves_per_eu=0):
+def make_tuning(bt=0, tile0=0, tile1=0, stream_chunk=0, cells_per_lane=0, rows_per_wave=0,
+                waves_per_eu=0):
     t = S5DTuning()
     t.struct_size = ctypes.sizeof(S5DTuning)
     t.bt, t.tile0, t.tile1 = int(bt), int(tile0), int(tile1)
-    t.stream_chunk, t.cells_per_lane, t.waves_per_eu = int(stream_chunk), int(cells_per_lane), int(waves_per_eu)
+    t.stream_chunk, t.cells_per_lane = int(stream_chunk), int(cells_per_lane)
+    t.rows_per_wave, t.waves_per_eu = int(rows_per_wave), int(waves_per_eu)
     return t

@@ -41,17 +41,24 @@ DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                 "-I" + CSRC, "-I" + INCLUDE]
 
-HOST_SOURCES = ["abi.cpp", "halo.hip"]
-HEADERS = ["s5d_internal.h", "sweep2d.h"]
+HOST_SOURCES = ["abi.cpp", "halo.hip", "norms.hip"]
+HEADERS = ["s5d_internal.h", "kcommon.h", "sweep2d.h", "sweep3d.h"]
+HOST_HEADERS = ["norms.h"]  # included by host sources only
 
-DTYPES = {0: ("f32", "float", 1), 1: ("f64", "double", 2)}
+# Kernel kinds: (name, C++ type, 32-bit words per element, accumulation
+# policy).  Kind 2 is float32 with compensated (Dot2) accumulation.
+DTYPES = {0: ("f32", "float", 1, 0), 1: ("f64", "double", 2, 0), 2: ("f32c", "float", 1, 1)}
 MAX_BT = 10
+# Compensated accumulation costs about nine VALU operations per term instead of
+# one FMA, so these kernels are bound by arithmetic already at small depth.
+MAX_BT_COMP = 4
 
 
-def est_vgprs_2d(words, box, r, cpl, bt, nr):
+def est_vgprs_2d(words, box, r, cpl, bt, nr, accw=1):
     """Lower bound of the register state of one 2D variant, in 32-bit VGPRs:
-    2r accumulator rows per level, the load ring, the extended row."""
-    return words * (bt * 2 * r * cpl + nr * cpl + cpl + 2 * r) + 16
+    2r accumulator rows per level (accw values per accumulator), the load
+    ring, the extended row."""
+    return words * (bt * 2 * r * cpl * accw + nr * cpl + cpl + 2 * r) + 16
 
 
 def ring_depth(r, bt, words):
@@ -68,18 +75,18 @@ def ring_depth(r, bt, words):
 def candidates_2d():
     """(dtype, box, r, cpl, bt, nr) tuples worth compiling."""
     out = []
-    for dtype, (_, _, words) in DTYPES.items():
-        cpls = (4,) if dtype == 0 else (2, 4)
+    for dtype, (_, _, words, acc) in DTYPES.items():
+        cpls = (2, 4) if dtype == 1 else (4,)
         for box, rmax in ((0, 4), (1, 2)):
             for r in range(1, rmax + 1):
                 for cpl in cpls:
                     if r > cpl:
                         continue
-                    for bt in range(1, MAX_BT + 1):
+                    for bt in range(1, (MAX_BT_COMP if acc else MAX_BT) + 1):
                         if 64 * cpl - 2 * bt * r < 16 * cpl:
                             continue
                         nr = ring_depth(r, bt, words)
-                        if est_vgprs_2d(words, box, r, cpl, bt, nr) > 224:
+                        if est_vgprs_2d(words, box, r, cpl, bt, nr, 1 + acc) > 224:
                             continue
                         out.append((dtype, box, r, cpl, bt, nr))
     return out
@@ -93,6 +100,57 @@ def variants_2d():
     if not rec:
         return candidates_2d()
     return [v for v in candidates_2d() if _vname(v) in rec and rec[_vname(v)]["ok"]]
+
+
+# 3D tile shapes per dtype: (cells per lane along axis 2, rows per wave along
+# axis 1, waves per workgroup); the tile is nw*m rows by 64*cpl columns.
+TILES_3D = {0: [(2, 4, 8), (2, 2, 16)], 1: [(2, 2, 8), (2, 4, 8)], 2: [(2, 2, 8), (2, 4, 8)]}
+MAX_BT_3D = {1: 5, 2: 3}
+
+
+def est_vgprs_3d(words, box, r, cpl, m, bt, nr, accw=1):
+    """Register state of one 3D variant: 2r accumulator (accw values each) and
+    r delay planes per level, the load ring and the extended plane, in 32-bit
+    VGPRs."""
+    cells = m * cpl
+    return words * (bt * (2 * accw + 1) * r * cells + nr * cells + (m + 2 * r) * (cpl + 2 * r)) + 24
+
+
+def candidates_3d():
+    """(dtype, box, r, cpl, m, nw, bt, nr) tuples worth compiling."""
+    out = []
+    for dtype, (_, _, words, acc) in DTYPES.items():
+        for box in (0, 1):
+            for r in (1, 2):
+                for cpl, m, nw in TILES_3D[dtype]:
+                    if r > cpl or r > m:
+                        continue
+                    # VGPR cap per lane: a workgroup of nw waves keeps ceil(nw/4)
+                    # waves on each SIMD of its CU
+                    cap = min(256, 512 // max(1, (nw + 3) // 4))
+                    for bt in range(1, min(MAX_BT_3D[r], 2 if acc else 99) + 1):
+                        c1, c2 = nw * m - 2 * bt * r, 64 * cpl - 2 * bt * r
+                        if c1 < (nw * m) // 3 or c2 < 16:
+                            continue
+                        if box and r == 2 and (bt > 2 or acc):
+                            continue
+                        if est_vgprs_3d(words, box, r, cpl, m, bt, 2, 1 + acc) > 0.85 * cap:
+                            continue
+                        out.append((dtype, box, r, cpl, m, nw, bt, 2))
+    return out
+
+
+def variants_3d():
+    rec = _load_resources()
+    if not rec:
+        return candidates_3d()
+    return [v for v in candidates_3d() if _vname3(v) in rec and rec[_vname3(v)]["ok"]]
+
+
+def _vname3(v):
+    dtype, box, r, cpl, m, nw, bt, nr = v
+    return "k3d_%s_%s_r%d_c%d_m%d_w%d_b%d_n%d" % (DTYPES[dtype][0], "box" if box else "star",
+                                                  r, cpl, m, nw, bt, nr)
 
 
 RESOURCES = os.path.join(HERE, "kernel_resources.json")
@@ -139,16 +197,27 @@ def _write_if_changed(path, text):
         f.write(text)
 
 
-def _generate(variants):
+def _generate(variants, variants3=()):
     inst = os.path.join(BUILD, "inst")
     os.makedirs(inst, exist_ok=True)
     units = []
+    for v in variants3:
+        dtype, box, r, cpl, m, nw, bt, nr = v
+        name = _vname3(v)
+        text = ('#include "sweep3d.h"\nnamespace s5d {\nKernel3D %s() {\n'
+                '  return make_kernel3d<%s, %d, %d, %s, %d, %d, %d, %d, %d>();\n}\n}  // namespace s5d\n'
+                % (name, DTYPES[dtype][1], DTYPES[dtype][3], r, "true" if box else "false", bt, cpl,
+                   m, nw, nr))
+        path = os.path.join(inst, name + ".hip")
+        _write_if_changed(path, text)
+        units.append(path)
     for v in variants:
         dtype, box, r, cpl, bt, nr = v
         name = _vname(v)
         text = ('#include "sweep2d.h"\nnamespace s5d {\nKernel2D %s() {\n'
-                '  return make_kernel2d<%s, %d, %s, %d, %d, %d>();\n}\n}  // namespace s5d\n'
-                % (name, DTYPES[dtype][1], r, "true" if box else "false", bt, cpl, nr))
+                '  return make_kernel2d<%s, %d, %d, %s, %d, %d, %d>();\n}\n}  // namespace s5d\n'
+                % (name, DTYPES[dtype][1], DTYPES[dtype][3], r, "true" if box else "false", bt,
+                   cpl, nr))
         path = os.path.join(inst, name + ".hip")
         _write_if_changed(path, text)
         units.append(path)
@@ -160,6 +229,15 @@ def _generate(variants):
         lines.append("  {%d, %d, %d, %d, %d, &%s}," % (dtype, box, r, cpl, bt, _vname(v)))
     lines.append("};")
     lines.append("const int kRegistry2DSize = %d;" % len(variants))
+    lines += ["Kernel3D %s();" % _vname3(v) for v in variants3]
+    lines.append("const Entry3D kRegistry3D[] = {")
+    for v in variants3:
+        dtype, box, r, cpl, m, nw, bt, nr = v
+        lines.append("  {%d, %d, %d, %d, %d, %d, %d, &%s}," % (dtype, box, r, cpl, m, nw, bt, _vname3(v)))
+    if not variants3:
+        lines.append("  {0, 0, 0, 0, 0, 0, 0, nullptr},")
+    lines.append("};")
+    lines.append("const int kRegistry3DSize = %d;" % len(variants3))
     lines.append("}  // namespace s5d")
     reg = os.path.join(BUILD, "registry.cpp")
     _write_if_changed(reg, "\n".join(lines) + "\n")
@@ -179,7 +257,7 @@ def _compile(src, header_digest, incremental):
     """Compile one unit; returns (object path, seconds, kernel resources)."""
     import json
     base = os.path.splitext(os.path.basename(src))[0]
-    key = _digest([src], DEVICE_FLAGS + [header_digest, "v5"])
+    key = _digest([src], DEVICE_FLAGS + [header_digest, "v6"])
     obj = os.path.join(BUILD, "obj", "%s.%s.o" % (base, key))
     meta = obj + ".res.json"
     if incremental and os.path.exists(obj) and os.path.exists(meta):
@@ -213,17 +291,20 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
     if not incremental and os.path.isdir(os.path.join(BUILD, "obj")):
         shutil.rmtree(os.path.join(BUILD, "obj"))
     cands = [v for v in candidates_2d() if only is None or re.search(only, _vname(v))]
-    units, _ = _generate(cands)
+    cands3 = [v for v in candidates_3d() if only is None or re.search(only, _vname3(v))]
+    units, _ = _generate(cands, cands3)
     hdr = _digest([os.path.join(CSRC, h) for h in HEADERS] +
                   [os.path.join(INCLUDE, "stencil5d.h")], [])
     jobs = jobs or max(1, min(32, os.cpu_count() or 1))
     t0 = time.time()
     objs, res_by_unit = {}, {}
     host = [os.path.join(CSRC, s) for s in HOST_SOURCES]
+    host_hdr = hdr + _digest([os.path.join(CSRC, h) for h in HOST_HEADERS], [])
     # longest first: the box and deep variants dominate the build time
     order = sorted(units, key=lambda p: (("box" not in p), -len(p))) + host
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        futs = {ex.submit(_compile, s, hdr, incremental): s for s in order}
+        futs = {ex.submit(_compile, s, host_hdr if s in host else hdr, incremental): s
+                for s in order}
         for fut in cf.as_completed(futs):
             obj, dt, resources = fut.result()
             src = futs[fut]
@@ -238,13 +319,19 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
         # tolerated (they cost register copies, not memory traffic)
         r["ok"] = r.get("scratch", 1) == 0 and r.get("vgprs", 999) <= 256 and r.get("agprs", 0) <= 128
         record[_vname(v)] = r
+    for v in cands3:
+        r = dict(res_by_unit.get(_vname3(v), {}))
+        r["ok"] = r.get("scratch", 1) == 0 and r.get("vgprs", 999) <= 256 and r.get("agprs", 0) <= 128
+        record[_vname3(v)] = r
     kept = [v for v in cands if record[_vname(v)]["ok"]]
-    _, reg = _generate(kept)
+    kept3 = [v for v in cands3 if record[_vname3(v)]["ok"]]
+    _, reg = _generate(kept, kept3)
     reg_obj, _, _ = _compile(reg, hdr, False)
     with open(RESOURCES, "w") as f:
         json.dump(record, f, indent=1, sort_keys=True)
     link = [objs[s] for s in host] + [reg_obj] + \
-        [objs[os.path.join(BUILD, "inst", _vname(v) + ".hip")] for v in kept]
+        [objs[os.path.join(BUILD, "inst", _vname(v) + ".hip")] for v in kept] + \
+        [objs[os.path.join(BUILD, "inst", _vname3(v) + ".hip")] for v in kept3]
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *link]
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
@@ -252,8 +339,8 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
         raise RuntimeError("link failed:\n" + res.stdout)
     os.replace(tmp, LIB)
     if verbose:
-        print("built %s: %d of %d candidate variants fit in registers, %.0f s"
-              % (LIB, len(kept), len(cands), time.time() - t0))
+        print("built %s: %d of %d 2D and %d of %d 3D candidate variants fit in registers, %.0f s"
+              % (LIB, len(kept), len(cands), len(kept3), len(cands3), time.time() - t0))
     return LIB
 
 
@@ -269,6 +356,8 @@ def main(argv=None):
         rec = _load_resources()
         for v in candidates_2d():
             print(_vname(v), rec.get(_vname(v), {}))
+        for v in candidates_3d():
+            print(_vname3(v), rec.get(_vname3(v), {}))
         return 0
     build(jobs=args.jobs, incremental=args.incremental, verbose=True, only=args.only)
     return 0

@@ -12,11 +12,17 @@
 #include <string>
 #include <vector>
 
+#include "norms.h"
 #include "s5d_internal.h"
 #include "stencil5d.h"
 
 using s5d::Entry2D;
+using s5d::Entry3D;
 using s5d::Kernel2D;
+using s5d::Kernel3D;
+using s5d::KIND_F32;
+using s5d::KIND_F32_COMP;
+using s5d::KIND_F64;
 
 namespace {
 
@@ -34,22 +40,40 @@ s5d_status device_fail(hipError_t e, const char* what) {
 // Largest radius with kernels, per dimensionality and shape.
 int max_radius(int ndim, int shape) {
   if (ndim == 2) return shape == S5D_STAR ? 4 : 2;
-  return 0;
+  return 2;
 }
 
-const Entry2D* find2d(int dtype, int box, int r, int cpl, int bt) {
-  for (int i = 0; i < s5d::kRegistry2DSize; ++i) {
-    const Entry2D& e = s5d::kRegistry2D[i];
-    if (e.dtype == dtype && e.box == box && e.r == r && e.cpl == cpl && e.bt == bt) return &e;
+const Entry3D* find3d(int kind, int box, int r, int cpl, int m, int nw, int bt) {
+  for (int i = 0; i < s5d::kRegistry3DSize; ++i) {
+    const Entry3D& e = s5d::kRegistry3D[i];
+    if (e.dtype == kind && e.box == box && e.r == r && e.cpl == cpl && e.m == m && e.nw == nw && e.bt == bt)
+      return &e;
   }
   return nullptr;
 }
 
-int max_bt2d(int dtype, int box, int r, int cpl) {
+// 3D defaults: the paper's scaling limits for 3D (star up to about 5, box up
+// to about 3 at radius 1; "Scaling Performance"), shallower at radius 2.
+int default_bt3(int kind, int box, int r) {
+  // compensated accumulation is bound by arithmetic from the first level on
+  if (kind == KIND_F32_COMP) return 1;
+  if (r == 1) return box ? 3 : 4;
+  return box ? 1 : 2;
+}
+
+const Entry2D* find2d(int kind, int box, int r, int cpl, int bt) {
+  for (int i = 0; i < s5d::kRegistry2DSize; ++i) {
+    const Entry2D& e = s5d::kRegistry2D[i];
+    if (e.dtype == kind && e.box == box && e.r == r && e.cpl == cpl && e.bt == bt) return &e;
+  }
+  return nullptr;
+}
+
+int max_bt2d(int kind, int box, int r, int cpl) {
   int best = 0;
   for (int i = 0; i < s5d::kRegistry2DSize; ++i) {
     const Entry2D& e = s5d::kRegistry2D[i];
-    if (e.dtype == dtype && e.box == box && e.r == r && e.cpl == cpl) best = std::max(best, e.bt);
+    if (e.dtype == kind && e.box == box && e.r == r && e.cpl == cpl) best = std::max(best, e.bt);
   }
   return best;
 }
@@ -62,15 +86,18 @@ int max_bt2d(int dtype, int box, int r, int cpl) {
 struct Default2D {
   int bt, cpl;
 };
-Default2D default_tuning(int dtype, int box, int r) {
+Default2D default_tuning(int kind, int box, int r) {
   static const Default2D f32_star[4] = {{10, 4}, {7, 4}, {4, 4}, {3, 4}};
   static const Default2D f32_box[2] = {{6, 4}, {3, 4}};
   static const Default2D f64_star[4] = {{9, 2}, {4, 2}, {3, 4}, {2, 4}};
   static const Default2D f64_box[2] = {{8, 2}, {3, 2}};
-  if (dtype == S5D_F32) return box ? f32_box[r - 1] : f32_star[r - 1];
+  static const Default2D comp_star[4] = {{3, 4}, {2, 4}, {2, 4}, {1, 4}};
+  static const Default2D comp_box[2] = {{2, 4}, {1, 4}};
+  if (kind == KIND_F32) return box ? f32_box[r - 1] : f32_star[r - 1];
+  if (kind == KIND_F32_COMP) return box ? comp_box[r - 1] : comp_star[r - 1];
   return box ? f64_box[r - 1] : f64_star[r - 1];
 }
-int default_bt(int dtype, int box, int r) { return default_tuning(dtype, box, r).bt; }
+int default_bt(int kind, int box, int r) { return default_tuning(kind, box, r).bt; }
 
 struct DeviceInfo {
   int cus = 256;
@@ -165,8 +192,122 @@ struct s5d_plan {
   int64_t padded[3];
   int64_t bytes;
   int elem;
-  Kernel2D by_bt[16];  // index bt: kernel for a round of bt steps (same cells per lane)
+  int kind;             // kernel kind: KIND_F32, KIND_F64 or KIND_F32_COMP
+  Kernel2D by_bt[16];   // 2D: index bt -> kernel for a round of bt steps (same tile)
+  Kernel3D by_bt3[16];  // 3D: likewise
 };
+
+namespace {
+
+s5d_status plan_2d(s5d_plan* p, const s5d_tuning& req, int box, int r) {
+  const s5d_desc& d = p->d;
+  int cpl = req.cells_per_lane;
+  if (req.tile0 > 0) {
+    if (req.tile0 % 64 != 0) return fail(S5D_EINVAL, "tile0 must be a multiple of 64 (one wave64 per tile)");
+    if (cpl > 0 && cpl * 64 != req.tile0) return fail(S5D_EINVAL, "tile0 != 64 * cells_per_lane");
+    cpl = req.tile0 / 64;
+  }
+  if (req.tile1 > 0 || req.rows_per_wave > 0) return fail(S5D_EINVAL, "tile1 and rows_per_wave are 3D fields");
+  int bt = req.bt;
+  if (cpl == 0 && (bt == 0 || bt == default_bt(p->kind, box, r))) {
+    const int c = default_tuning(p->kind, box, r).cpl;
+    if (max_bt2d(p->kind, box, r, c) >= default_bt(p->kind, box, r)) cpl = c;
+  }
+  if (cpl == 0) {
+    // widest tile that still reaches the requested (or default) depth
+    const int want = bt > 0 ? bt : default_bt(p->kind, box, r);
+    int best_cpl = 0, best_bt = 0;
+    for (int c : {4, 2, 8}) {
+      const int mb = std::min(want, max_bt2d(p->kind, box, r, c));
+      if (mb > best_bt) {
+        best_bt = mb;
+        best_cpl = c;
+      }
+    }
+    if (best_cpl == 0) return fail(S5D_EUNSUPPORTED, "no kernel variant for this stencil");
+    cpl = best_cpl;
+  }
+  const int bt_cap = max_bt2d(p->kind, box, r, cpl);
+  if (bt_cap == 0) return fail(S5D_EUNSUPPORTED, "no kernel with cells_per_lane=" + std::to_string(cpl));
+  if (bt == 0) bt = std::min(default_bt(p->kind, box, r), bt_cap);
+  if (bt > bt_cap)
+    return fail(S5D_EUNSUPPORTED, "bt=" + std::to_string(bt) + " exceeds the deepest kernel built for this stencil (" +
+                                      std::to_string(bt_cap) + ")");
+  if (d.steps > 0 && bt > d.steps) bt = static_cast<int>(d.steps);
+  for (int b = 1; b <= bt; ++b) {
+    const Entry2D* e = find2d(p->kind, box, r, cpl, b);
+    if (!e) return fail(S5D_EUNSUPPORTED, "kernel variant missing for bt=" + std::to_string(b));
+    p->by_bt[b] = e->make();
+  }
+  int chunk = req.stream_chunk;
+  if (chunk == 0) {
+    const DeviceInfo dev = query_device();
+    int occ = dev.ok ? p->by_bt[bt].occupancy() : 0;
+    if (occ <= 0) occ = 2;
+    const int64_t C = 64LL * cpl - 2LL * bt * r;
+    const int64_t ntiles = (d.interior[1] + C - 1) / C;
+    const int64_t slots = static_cast<int64_t>(dev.cus) * occ * s5d::kWavesPerBlock;
+    chunk = choose_chunk(d.interior[0], ntiles, slots, bt, r);
+  }
+  if (chunk < 1) return fail(S5D_EINVAL, "stream_chunk must be >= 1");
+  p->tun.bt = bt;
+  p->tun.tile0 = 64 * cpl;
+  p->tun.stream_chunk = chunk;
+  p->tun.cells_per_lane = cpl;
+  return S5D_OK;
+}
+
+s5d_status plan_3d(s5d_plan* p, const s5d_tuning& req, int box, int r) {
+  const s5d_desc& d = p->d;
+  // tile shape: the (cells per lane, rows per wave, waves) family built for
+  // this stencil; explicit fields must match one of them
+  const Entry3D* fam = nullptr;
+  int bt_cap = 0;
+  for (int i = 0; i < s5d::kRegistry3DSize; ++i) {
+    const Entry3D& e = s5d::kRegistry3D[i];
+    if (e.dtype != p->kind || e.box != box || e.r != r) continue;
+    if (req.cells_per_lane > 0 && e.cpl != req.cells_per_lane) continue;
+    if (req.rows_per_wave > 0 && e.m != req.rows_per_wave) continue;
+    if (req.tile0 > 0 && e.m * e.nw != req.tile0) continue;
+    if (req.tile1 > 0 && 64 * e.cpl != req.tile1) continue;
+    if (!fam || (e.cpl == fam->cpl && e.m == fam->m && e.nw == fam->nw)) {
+      fam = &e;
+      bt_cap = std::max(bt_cap, e.bt);
+    }
+  }
+  if (!fam) return fail(S5D_EUNSUPPORTED, "no 3D kernel for this stencil and tile shape");
+  int bt = req.bt > 0 ? req.bt : std::min(default_bt3(p->kind, box, r), bt_cap);
+  if (bt > bt_cap)
+    return fail(S5D_EUNSUPPORTED, "bt=" + std::to_string(bt) + " exceeds the deepest 3D kernel built (" +
+                                      std::to_string(bt_cap) + ")");
+  if (d.steps > 0 && bt > d.steps) bt = static_cast<int>(d.steps);
+  for (int b = 1; b <= bt; ++b) {
+    const Entry3D* e = find3d(p->kind, box, r, fam->cpl, fam->m, fam->nw, b);
+    if (!e) return fail(S5D_EUNSUPPORTED, "3D kernel variant missing for bt=" + std::to_string(b));
+    p->by_bt3[b] = e->make();
+  }
+  const int B1 = fam->m * fam->nw, B2 = 64 * fam->cpl;
+  int chunk = req.stream_chunk;
+  if (chunk == 0) {
+    const DeviceInfo dev = query_device();
+    int occ = dev.ok ? p->by_bt3[bt].occupancy() : 0;
+    if (occ <= 0) occ = 1;
+    const int64_t C1 = B1 - 2LL * bt * r, C2 = B2 - 2LL * bt * r;
+    const int64_t ntiles = ((d.interior[1] + C1 - 1) / C1) * ((d.interior[2] + C2 - 1) / C2);
+    const int64_t slots = static_cast<int64_t>(dev.cus) * occ;  // resident workgroups
+    chunk = choose_chunk(d.interior[0], ntiles, slots, bt, r);
+  }
+  if (chunk < 1) return fail(S5D_EINVAL, "stream_chunk must be >= 1");
+  p->tun.bt = bt;
+  p->tun.tile0 = B1;
+  p->tun.tile1 = B2;
+  p->tun.stream_chunk = chunk;
+  p->tun.cells_per_lane = fam->cpl;
+  p->tun.rows_per_wave = fam->m;
+  return S5D_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -238,44 +379,9 @@ s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_p
 
   if (d.radius > max_radius(d.ndim, d.shape))
     return fail(S5D_EUNSUPPORTED, "no kernel for this dimensionality/shape/radius");
-  if (d.accum == S5D_ACC_COMPENSATED) return fail(S5D_EUNSUPPORTED, "no compensated-accumulation kernel built");
 
   const int box = d.shape == S5D_BOX ? 1 : 0;
   const int r = d.radius;
-  // cells per lane
-  int cpl = req.cells_per_lane;
-  if (req.tile0 > 0) {
-    if (req.tile0 % 64 != 0) return fail(S5D_EINVAL, "tile0 must be a multiple of 64 (one wave64 per tile)");
-    if (cpl > 0 && cpl * 64 != req.tile0) return fail(S5D_EINVAL, "tile0 != 64 * cells_per_lane");
-    cpl = req.tile0 / 64;
-  }
-  int bt = req.bt;
-  if (cpl == 0 && (bt == 0 || bt == default_bt(d.dtype, box, r))) {
-    const int c = default_tuning(d.dtype, box, r).cpl;
-    if (max_bt2d(d.dtype, box, r, c) >= default_bt(d.dtype, box, r)) cpl = c;
-  }
-  if (cpl == 0) {
-    // widest tile that still reaches the requested (or default) depth
-    const int want = bt > 0 ? bt : default_bt(d.dtype, box, r);
-    int best_cpl = 0, best_bt = 0;
-    for (int c : {4, 2, 8}) {
-      const int mb = std::min(want, max_bt2d(d.dtype, box, r, c));
-      if (mb > best_bt) {
-        best_bt = mb;
-        best_cpl = c;
-      }
-    }
-    if (best_cpl == 0) return fail(S5D_EUNSUPPORTED, "no kernel variant for this stencil");
-    cpl = best_cpl;
-  }
-  const int bt_cap = max_bt2d(d.dtype, box, r, cpl);
-  if (bt_cap == 0) return fail(S5D_EUNSUPPORTED, "no kernel with cells_per_lane=" + std::to_string(cpl));
-  if (bt == 0) bt = std::min(default_bt(d.dtype, box, r), bt_cap);
-  if (bt > bt_cap)
-    return fail(S5D_EUNSUPPORTED, "bt=" + std::to_string(bt) + " exceeds the deepest kernel built for this stencil (" +
-                                      std::to_string(bt_cap) + ")");
-  if (d.steps > 0 && bt > d.steps) bt = static_cast<int>(d.steps);
-
   s5d_plan* p = new (std::nothrow) s5d_plan;
   if (!p) return fail(S5D_ENOMEM, "plan allocation failed");
   p->d = d;
@@ -288,39 +394,19 @@ s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_p
   p->d.coeffs = nullptr;
   for (int a = 0; a < 3; ++a) p->padded[a] = padded[a];
   p->elem = d.dtype == S5D_F32 ? 4 : 8;
+  p->kind = d.accum == S5D_ACC_COMPENSATED ? KIND_F32_COMP : d.dtype == S5D_F32 ? KIND_F32 : KIND_F64;
   p->bytes = total * p->elem;
-  for (int b = 0; b < 16; ++b) p->by_bt[b] = Kernel2D{nullptr, nullptr, 0, 0, 0};
-  for (int b = 1; b <= bt; ++b) {
-    const Entry2D* e = find2d(d.dtype, box, r, cpl, b);
-    if (!e) {
-      delete p;
-      return fail(S5D_EUNSUPPORTED, "kernel variant missing for bt=" + std::to_string(b));
-    }
-    p->by_bt[b] = e->make();
-  }
-
-  int chunk = req.stream_chunk;
-  if (chunk == 0) {
-    const DeviceInfo dev = query_device();
-    int occ = dev.ok ? p->by_bt[bt].occupancy() : 0;
-    if (occ <= 0) occ = 2;
-    const int64_t C = 64LL * cpl - 2LL * bt * r;
-    const int64_t ntiles = (d.interior[1] + C - 1) / C;
-    const int64_t slots = static_cast<int64_t>(dev.cus) * occ * s5d::kWavesPerBlock;
-    chunk = choose_chunk(d.interior[0], ntiles, slots, bt, r);
-  }
-  if (chunk < 1) {
-    delete p;
-    return fail(S5D_EINVAL, "stream_chunk must be >= 1");
+  for (int b = 0; b < 16; ++b) {
+    p->by_bt[b] = Kernel2D{nullptr, nullptr, 0, 0, 0};
+    p->by_bt3[b] = Kernel3D{nullptr, nullptr, 0, 0, 0, 0};
   }
   std::memset(&p->tun, 0, sizeof(p->tun));
   p->tun.struct_size = sizeof(s5d_tuning);
-  p->tun.bt = bt;
-  p->tun.tile0 = 64 * cpl;
-  p->tun.tile1 = 0;
-  p->tun.stream_chunk = chunk;
-  p->tun.cells_per_lane = cpl;
-  p->tun.waves_per_eu = 0;
+  const s5d_status st = d.ndim == 2 ? plan_2d(p, req, box, r) : plan_3d(p, req, box, r);
+  if (st != S5D_OK) {
+    delete p;
+    return st;
+  }
   *out = p;
   return S5D_OK;
 }
@@ -355,14 +441,38 @@ s5d_status s5d_run(const s5d_plan* plan, void* buf0, void* buf1, void* stream, i
   if (e != hipSuccess) return device_fail(e, "boundary copy launch");
 
   const RoundSchedule rs = schedule_rounds(T, plan->tun.bt);
+  void* bufs[2] = {buf0, buf1};
+  int64_t k = 0;
+  if (plan->d.ndim == 3) {
+    s5d::Round3D rd;
+    rd.I0 = static_cast<int32_t>(plan->d.interior[0]);
+    rd.I1 = static_cast<int32_t>(plan->d.interior[1]);
+    rd.I2 = static_cast<int32_t>(plan->d.interior[2]);
+    rd.chunk = plan->tun.stream_chunk;
+    rd.coeffs = plan->coeffs.data();
+    rd.stream = st;
+    auto one3 = [&](int bt) -> hipError_t {
+      rd.src = bufs[k % 2];
+      rd.dst = bufs[(k + 1) % 2];
+      ++k;
+      return plan->by_bt3[bt].launch(rd);
+    };
+    for (int64_t i = 0; i < rs.n_full; ++i) {
+      e = one3(rs.bt);
+      if (e != hipSuccess) return device_fail(e, "sweep launch");
+    }
+    for (int i = 0; i < rs.n_tail; ++i) {
+      e = one3(rs.tail[i]);
+      if (e != hipSuccess) return device_fail(e, "sweep launch");
+    }
+    return S5D_OK;
+  }
   s5d::Round2D rd;
   rd.I0 = static_cast<int32_t>(plan->d.interior[0]);
   rd.I1 = static_cast<int32_t>(plan->d.interior[1]);
   rd.chunk = plan->tun.stream_chunk;
   rd.coeffs = plan->coeffs.data();
   rd.stream = st;
-  void* bufs[2] = {buf0, buf1};
-  int64_t k = 0;
   auto one = [&](int bt) -> hipError_t {
     rd.src = bufs[k % 2];
     rd.dst = bufs[(k + 1) % 2];
@@ -377,6 +487,34 @@ s5d_status s5d_run(const s5d_plan* plan, void* buf0, void* buf1, void* stream, i
     e = one(rs.tail[i]);
     if (e != hipSuccess) return device_fail(e, "sweep launch");
   }
+  return S5D_OK;
+}
+
+int64_t s5d_error_norms_workspace_bytes(int64_t n) {
+  if (n < 0) return -1;
+  return static_cast<int64_t>(s5d::error_norms_parts(n)) * 5 * static_cast<int64_t>(sizeof(double));
+}
+
+s5d_status s5d_error_norms(const void* got, int32_t got_dtype, const void* ref, int32_t ref_dtype, int64_t n,
+                           double* out, void* workspace, int64_t workspace_bytes, void* stream) {
+  g_last_error.clear();
+  if (n < 0) return fail(S5D_EINVAL, "n must be >= 0");
+  if ((got_dtype != S5D_F32 && got_dtype != S5D_F64) || (ref_dtype != S5D_F32 && ref_dtype != S5D_F64))
+    return fail(S5D_EINVAL, "dtypes must be S5D_F32 or S5D_F64");
+  if (!out || !workspace) return fail(S5D_EINVAL, "out and workspace must not be NULL");
+  if (n > 0 && (!got || !ref)) return fail(S5D_EINVAL, "got and ref must not be NULL");
+  if ((n > 0 && ((reinterpret_cast<uintptr_t>(got) | reinterpret_cast<uintptr_t>(ref)) & 15)) ||
+      ((reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(workspace)) & 7))
+    return fail(S5D_EINVAL, "got and ref must be 16-byte aligned, out and workspace 8-byte aligned");
+  if (workspace_bytes < s5d_error_norms_workspace_bytes(n))
+    return fail(S5D_EINVAL, "workspace smaller than s5d_error_norms_workspace_bytes(n)");
+  const uintptr_t o0 = reinterpret_cast<uintptr_t>(out), w0 = reinterpret_cast<uintptr_t>(workspace);
+  if (o0 < w0 + static_cast<uintptr_t>(workspace_bytes) && w0 < o0 + S5D_NORMS_COUNT * sizeof(double))
+    return fail(S5D_EINVAL, "out overlaps the workspace");
+  const hipError_t e = s5d::launch_error_norms(got, got_dtype == S5D_F64, ref, ref_dtype == S5D_F64, n, out,
+                                               static_cast<double*>(workspace), s5d::error_norms_parts(n),
+                                               static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "error-norm launch");
   return S5D_OK;
 }
 

@@ -53,8 +53,11 @@ struct Kernel2D {
 
 // One compiled 2D kernel variant.  The build enumerates the variants (one
 // object file each) and writes the table kRegistry2D.
+// Kernel kinds: the element type and the accumulation policy of a variant.
+enum { KIND_F32 = 0, KIND_F64 = 1, KIND_F32_COMP = 2 };
+
 struct Entry2D {
-  int dtype;   // 0 = float32, 1 = float64
+  int dtype;   // kernel kind: KIND_F32, KIND_F64 or KIND_F32_COMP
   int box;     // 0 = star, 1 = box
   int r;
   int cpl;
@@ -63,6 +66,43 @@ struct Entry2D {
 };
 extern const Entry2D kRegistry2D[];
 extern const int kRegistry2DSize;
+
+// Everything one launch of a 3D round needs besides the coefficients.
+struct Round3D {
+  const void* src;
+  void* dst;
+  int32_t I0, I1, I2;  // interior extents (axis 0 streams)
+  int32_t chunk;       // h_SN: output planes per stream block
+  const double* coeffs;
+  hipStream_t stream;
+};
+
+struct Sweep3DArgs {
+  const void* src;
+  void* dst;
+  int32_t I0, I1, I2;
+  int32_t nt1, nt2;  // tiles along axes 1 and 2
+  int32_t chunk;
+};
+
+using Launch3DFn = hipError_t (*)(const Round3D&);
+
+struct Kernel3D {
+  Launch3DFn launch;
+  Occupancy2DFn occupancy;  // resident workgroups per CU
+  int cpl;                  // cells per lane along axis 2
+  int m;                    // rows per wave along axis 1
+  int nw;                   // waves per workgroup (tile rows = nw * m)
+  int bt;
+};
+
+struct Entry3D {
+  int dtype;  // kernel kind, as for Entry2D
+  int box, r, cpl, m, nw, bt;
+  Kernel3D (*make)();
+};
+extern const Entry3D kRegistry3D[];
+extern const int kRegistry3DSize;
 
 // Copy the boundary cells (width r on every face) of a padded grid.
 hipError_t launch_halo_copy(const void* src, void* dst, int elem_bytes, int ndim,

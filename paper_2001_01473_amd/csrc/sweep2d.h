@@ -44,119 +44,9 @@
 //    and the masked cells into no-ops without a branch.
 #pragma once
 
-#include <hip/hip_runtime.h>
-#include <stdint.h>
-
-#include <type_traits>
-#include <utility>
-
-#include "s5d_internal.h"
-
-// Every lambda of the kernel bodies must be inlined: their arrays are register
-// state and only become registers (not scratch memory) once inlined.
-#define S5D_INL __attribute__((always_inline))
+#include "kcommon.h"
 
 namespace s5d {
-
-template <int N>
-using ic = std::integral_constant<int, N>;
-
-template <typename F, int... Is>
-__device__ __forceinline__ void sfor_impl(F&& f, std::integer_sequence<int, Is...>) {
-  (f(ic<Is>{}), ...);
-}
-// Compile-time loop: f(ic<0>{}), ..., f(ic<N-1>{}).
-template <int N, typename F>
-__device__ __forceinline__ void sfor(F&& f) {
-  sfor_impl(f, std::make_integer_sequence<int, N>{});
-}
-
-constexpr int pmod(int a, int m) { return ((a % m) + m) % m; }
-constexpr int gcd_i(int a, int b) { return b == 0 ? a : gcd_i(b, a % b); }
-constexpr int lcm_i(int a, int b) { return a / gcd_i(a, b) * b; }
-
-// DPP whole-wavefront shifts by one lane.  wave_shr:1 (0x138) hands lane l
-// the value of lane l-1; wave_shl:1 (0x130) hands lane l the value of lane
-// l+1.  bound_ctrl makes the lane without a source read 0, so no old value
-// has to be materialised.
-__device__ __forceinline__ int lane_from_lower_i32(int v) {
-  return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true);
-}
-__device__ __forceinline__ int lane_from_upper_i32(int v) {
-  return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true);
-}
-__device__ __forceinline__ float lane_from_lower(float v) {
-  return __int_as_float(lane_from_lower_i32(__float_as_int(v)));
-}
-__device__ __forceinline__ float lane_from_upper(float v) {
-  return __int_as_float(lane_from_upper_i32(__float_as_int(v)));
-}
-__device__ __forceinline__ double lane_from_lower(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = lane_from_lower_i32(static_cast<int>(b));
-  const int hi = lane_from_lower_i32(static_cast<int>(b >> 32));
-  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-__device__ __forceinline__ double lane_from_upper(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = lane_from_upper_i32(static_cast<int>(b));
-  const int hi = lane_from_upper_i32(static_cast<int>(b >> 32));
-  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-
-__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-// Buffer descriptors (gfx9 family: 3rd dword 0x00020000, raw byte
-// addressing).  An access whose byte offset is >= nbytes reads 0 / is dropped.
-constexpr uint32_t kOutOfRange = 0x80000000u;
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t nbytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), static_cast<short>(0),
-                                           static_cast<int>(nbytes), 0x00020000);
-}
-__device__ __forceinline__ void buf_load(float& v, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
-  v = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, static_cast<int>(off), 0, 0));
-}
-__device__ __forceinline__ void buf_load(double& v, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
-  v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, static_cast<int>(off), 0, 0));
-}
-__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
-  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, static_cast<int>(off), 0, 0);
-}
-__device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
-  using u2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(rs, 0, 0, 0));
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, static_cast<int>(off), 0, 0);
-}
-// A lane's CPL consecutive cells as 16-byte stores (CPL*sizeof(T) is a
-// multiple of 16); an out-of-range offset drops the whole vector.
-template <typename T, int CPL>
-__device__ __forceinline__ void buf_store_lane(const T (&v)[CPL], __amdgpu_buffer_rsrc_t rs, uint32_t off) {
-  static_assert((CPL * sizeof(T)) % 16 == 0, "lane vector must be whole 16-byte pieces");
-  using u4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(rs, 0, 0, 0));
-  constexpr int PER = 16 / sizeof(T);
-#pragma unroll
-  for (int q = 0; q < CPL / PER; ++q) {
-    T piece[PER];
-#pragma unroll
-    for (int j = 0; j < PER; ++j) piece[j] = v[q * PER + j];
-    const uint32_t o = off == kOutOfRange ? kOutOfRange : off + q * 16u;
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, piece), rs, static_cast<int>(o), 0, 0);
-  }
-}
-
-// A lane's CPL consecutive cells, element-aligned, read as one vector access.
-template <typename T, int N>
-struct __attribute__((packed, aligned(sizeof(T)))) LaneVec {
-  T v[N];
-};
-
-// Workgroups are dispatched round-robin over the 8 XCDs; renumber them so
-// that consecutive logical blocks (neighbouring tiles, which share BT*R
-// overlap columns) run on the same XCD and share its L2.
-__device__ __forceinline__ int xcd_logical_block(int b, int nblk) {
-  const int q = nblk >> 3, rem = nblk & 7, x = b & 7, i = b >> 3;
-  return x < rem ? x * (q + 1) + i : rem * (q + 1) + (x - rem) * q + i;
-}
 
 // Per-wave LDS stash of the boundary-column cells of the last BT*R+1 rows,
 // used by EDGE waves only: lane vectors of the (at most 4) lanes that hold
@@ -166,7 +56,7 @@ struct alignas(16) EdgeStash {
   T cols[BT * R + 1][4][CPL];
 };
 
-template <typename T, int R, bool BOX, int BT, int CPL, int NR, bool EDGE>
+template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR, bool EDGE>
 __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPack<T, npts(2, R, BOX)>& cf,
                                              int lane, int tile, int chunk, EdgeStash<T, R, BT, CPL>* stash) {
   constexpr int NA = 2 * R;         // pending output rows per level
@@ -232,10 +122,10 @@ __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPac
     }
   };
 
-  T acc[BT][NA][CPL];
+  Accum<T, ACC> acc[BT][NA][CPL];
   using RowV = T __attribute__((ext_vector_type(CPL)));
   RowV ringv[NR];
-  sfor<BT>([&](auto L) S5D_INL { sfor<NA>([&](auto S) S5D_INL { sfor<CPL>([&](auto K) S5D_INL { acc[L][S][K] = T(0); }); }); });
+  sfor<BT>([&](auto L) S5D_INL { sfor<NA>([&](auto S) S5D_INL { sfor<CPL>([&](auto K) S5D_INL { acc[L][S][K].zero(); }); }); });
 
   const int s_lo = max(0, row_a - BT * R);
   const int s0 = s_lo - s_lo % NS;    // step phases line up with accumulator slots
@@ -269,7 +159,7 @@ __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPac
         constexpr int lv = LI + 1;                       // level receiving row p = s-(lv-1)*R
         constexpr int pm = pmod(PH - (lv - 1) * R, NA);  // p mod 2R
         constexpr int so = pmod(pm + R, NA);             // slot of rows p-R and p+R
-        T(&A)[NA][CPL] = acc[LI];
+        Accum<T, ACC>(&A)[NA][CPL] = acc[LI];
 
         T E[XL];
         sfor<CPL>([&](auto K) S5D_INL { E[R + K] = cur[K]; });
@@ -279,30 +169,30 @@ __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPac
         });
 
         // contribution of the arriving row to the output d0 rows before it
-        auto add_row = [&](auto D0, T& acc_k, auto K, auto FIRST) S5D_INL {
+        auto add_row = [&](auto D0, Accum<T, ACC>& acc_k, auto K, auto FIRST) S5D_INL {
           constexpr int d0 = D0;
           constexpr bool first = FIRST;
           if constexpr (BOX) {
             sfor<2 * R + 1>([&](auto D1) S5D_INL {
               constexpr int ci = (d0 + R) * (2 * R + 1) + D1;
-              if constexpr (first && D1 == 0) acc_k = cf.c[ci] * E[K + D1];
-              else acc_k = fmadd(cf.c[ci], E[K + D1], acc_k);
+              if constexpr (first && D1 == 0) acc_k.first(cf.c[ci], E[K + D1]);
+              else acc_k.add(cf.c[ci], E[K + D1]);
             });
           } else if constexpr (d0 != 0) {
             constexpr int ci = d0 < 0 ? d0 + R : 3 * R + d0;
-            if constexpr (first) acc_k = cf.c[ci] * cur[K];
-            else acc_k = fmadd(cf.c[ci], cur[K], acc_k);
+            if constexpr (first) acc_k.first(cf.c[ci], cur[K]);
+            else acc_k.add(cf.c[ci], cur[K]);
           } else {
-            sfor<2 * R + 1>([&](auto D1) S5D_INL { acc_k = fmadd(cf.c[R + D1], E[K + D1], acc_k); });
+            sfor<2 * R + 1>([&](auto D1) S5D_INL { acc_k.add(cf.c[R + D1], E[K + D1]); });
           }
         };
 
         // 1. output p-R receives its last contribution (d0 = +R) and leaves
         T out[CPL];
         sfor<CPL>([&](auto K) S5D_INL {
-          T v = A[so][K];
+          Accum<T, ACC> v = A[so][K];
           add_row(ic<R>{}, v, K, std::false_type{});
-          out[K] = v;
+          out[K] = v.value();
         });
         // 2. output p+R starts in the freed slot (d0 = -R)
         sfor<CPL>([&](auto K) S5D_INL { add_row(ic<-R>{}, A[so][K], K, std::true_type{}); });
@@ -314,7 +204,8 @@ __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPac
         });
 
 
-        if constexpr (EDGE) {
+        if constexpr (EDGE && lv < BT) {
+          // the last level is only stored, and boundary cells are never stored
           const int o = s - lv * R;
           if (o < R || o >= I0 + R) {
             // boundary row: never written, so the source buffer still holds it
@@ -350,7 +241,7 @@ __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPac
   for (int it = 1; it < niter; ++it) iteration(s0 + it * NS);
 }
 
-template <typename T, int R, bool BOX, int BT, int CPL, int NR>
+template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void sweep2d_kernel(Sweep2DArgs a,
                                                                     CoefPack<T, npts(2, R, BOX)> cf) {
   constexpr int W = 64 * CPL;
@@ -373,12 +264,12 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void sweep2d_kernel(Sweep2DArg
   const bool edge = col0 < 0 || col0 + W > P1 || row_a - (BT - 1) * R < R ||
                     row_b + (BT - 1) * R > a.I0 + R;
   if (edge)
-    sweep2d_body<T, R, BOX, BT, CPL, NR, true>(a, cf, lane, tile, chunk, &stash[wib]);
+    sweep2d_body<T, ACC, R, BOX, BT, CPL, NR, true>(a, cf, lane, tile, chunk, &stash[wib]);
   else
-    sweep2d_body<T, R, BOX, BT, CPL, NR, false>(a, cf, lane, tile, chunk, &stash[wib]);
+    sweep2d_body<T, ACC, R, BOX, BT, CPL, NR, false>(a, cf, lane, tile, chunk, &stash[wib]);
 }
 
-template <typename T, int R, bool BOX, int BT, int CPL, int NR>
+template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
 hipError_t launch_sweep2d(const Round2D& rd) {
   constexpr int NP = npts(2, R, BOX);
   constexpr int C = 64 * CPL - 2 * BT * R;
@@ -395,23 +286,23 @@ hipError_t launch_sweep2d(const Round2D& rd) {
   a.nwaves = a.ntiles * nchunks;
   a.pad = 0;
   const int nblk = (a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
-  hipLaunchKernelGGL((sweep2d_kernel<T, R, BOX, BT, CPL, NR>), dim3(nblk), dim3(64 * kWavesPerBlock), 0,
+  hipLaunchKernelGGL((sweep2d_kernel<T, ACC, R, BOX, BT, CPL, NR>), dim3(nblk), dim3(64 * kWavesPerBlock), 0,
                      rd.stream, a, cf);
   return hipGetLastError();
 }
 
-template <typename T, int R, bool BOX, int BT, int CPL, int NR>
+template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
 int occupancy_sweep2d() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep2d_kernel<T, R, BOX, BT, CPL, NR>,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep2d_kernel<T, ACC, R, BOX, BT, CPL, NR>,
                                                    64 * kWavesPerBlock, 0) != hipSuccess)
     return 0;
   return nb;
 }
 
-template <typename T, int R, bool BOX, int BT, int CPL, int NR>
+template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
 Kernel2D make_kernel2d() {
-  return Kernel2D{&launch_sweep2d<T, R, BOX, BT, CPL, NR>, &occupancy_sweep2d<T, R, BOX, BT, CPL, NR>, CPL, BT,
+  return Kernel2D{&launch_sweep2d<T, ACC, R, BOX, BT, CPL, NR>, &occupancy_sweep2d<T, ACC, R, BOX, BT, CPL, NR>, CPL, BT,
                   64 * CPL};
 }
 

@@ -153,3 +153,26 @@ def test_status_strings():
     assert _lib.status_string(_lib.S5D_OK) == "S5D_OK"
     assert _lib.status_string(_lib.S5D_EUNSUPPORTED) == "S5D_EUNSUPPORTED"
     assert _lib.status_string(99) == "S5D_UNKNOWN"
+
+
+def test_error_norms_validation():
+    lib = _lib.load()
+    vp = ctypes.c_void_p
+    g, o, out, ws = vp(0x10000), vp(0x20000), vp(0x30000), vp(0x40000)
+    need = lib.s5d_error_norms_workspace_bytes(1000)
+    assert need == 40 and lib.s5d_error_norms_workspace_bytes(-1) == -1
+    assert lib.s5d_error_norms_workspace_bytes(1 << 40) == 2048 * 40
+    cases = [
+        (g, 0, o, 1, -1, out, ws, need),          # n < 0
+        (g, 2, o, 1, 1000, out, ws, need),        # bad dtype
+        (g, 0, o, 1, 1000, vp(0), ws, need),      # out NULL
+        (g, 0, o, 1, 1000, out, vp(0), need),     # workspace NULL
+        (vp(0), 0, o, 1, 1000, out, ws, need),    # got NULL
+        (vp(0x10004), 0, o, 1, 1000, out, ws, need),  # got misaligned
+        (g, 0, o, 1, 1000, out, ws, need - 8),    # workspace too small
+        (g, 0, o, 1, 1000, vp(0x40008), ws, need),  # out inside the workspace
+    ]
+    for args in cases:
+        st = lib.s5d_error_norms(*args, None)
+        assert st == _lib.S5D_EINVAL, args
+        assert _lib.last_error()

@@ -148,3 +148,85 @@ def test_threads_do_not_change_bits():
     a = oracle.sweep(case.grid, radius=1, box=True, coeffs=case.coeffs, steps=4, threads=1)
     b = oracle.sweep(case.grid, radius=1, box=True, coeffs=case.coeffs, steps=4, threads=4)
     np.testing.assert_array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# Compensated float32 accumulation (Dot2 of Ogita, Rump and Oishi, 2005).
+# ---------------------------------------------------------------------------
+
+def osweep_comp(a0, *, radius, box, coeffs, steps):
+    return oracle.sweep(a0, radius=radius, box=box, coeffs=coeffs, steps=steps,
+                        accum="compensated")
+
+
+@pytest.mark.parametrize("ndim,radius,box", [(2, 1, False), (2, 2, True), (3, 1, True)])
+def test_dot2_dyadic_exact(ndim, radius, box):
+    interior = (13, 11) if ndim == 2 else (5, 6, 7)
+    pins.check_dyadic_exact(osweep_comp, ndim, radius, box, interior, dtype=np.float32)
+
+
+def _exact_step_f32(grid, radius, box, c32):
+    """Exact rational value of one step's sum at every interior cell."""
+    from fractions import Fraction
+    nd = grid.ndim
+    offs = pins.canon_offsets(nd, radius, box)
+    cf = [Fraction(float(c)) for c in c32]
+    out, absum = {}, {}
+    inner = [idx for idx in np.ndindex(grid.shape)
+             if all(radius <= idx[a] < grid.shape[a] - radius for a in range(nd))]
+    for p in inner:
+        s, a = Fraction(0), Fraction(0)
+        for c, o in zip(cf, offs):
+            x = Fraction(float(grid[tuple(p[a] + o[a] for a in range(nd))]))
+            s += c * x
+            a += abs(c * x)
+        out[p], absum[p] = s, a
+    return out, absum
+
+
+@pytest.mark.parametrize("ndim,radius,box,interior", [
+    (2, 1, False, (9, 10)), (2, 2, True, (7, 8)), (3, 1, True, (4, 5, 5))])
+def test_dot2_single_step_bound_and_rounding(ndim, radius, box, interior):
+    """|res - exact| <= u|exact| + gamma_n^2 sum|c x| per cell (the published
+    bound), and res equals the correctly rounded exact sum in almost every cell."""
+    case = si.make_case(61, ndim, radius, box, interior, 1)
+    c32, g32 = case.as_dtype(np.float32)
+    # signed coefficients make the sums ill-conditioned, where compensation matters
+    rng = np.random.default_rng(3)
+    c32 = (c32 * np.where(rng.random(c32.size) < 0.5, -1, 1)).astype(np.float32)
+    got = oracle.sweep(g32, radius=radius, box=box, coeffs=c32, steps=1, accum="compensated")
+    plain = oracle.sweep(g32, radius=radius, box=box, coeffs=c32, steps=1)
+    exact, absum = _exact_step_f32(g32, radius, box, c32)
+    n = len(c32)
+    u = pins.U32
+    g2 = pins.gamma(n, u) ** 2
+    hits = plain_hits = 0
+    for p, e in exact.items():
+        err = abs(float(got[p]) - float(e))
+        assert err <= u * abs(float(e)) + g2 * float(absum[p]) + 1e-45, (p, err)
+        rn = np.float32(float(e))  # exact -> nearest float64 -> nearest float32
+        hits += int(got[p] == rn)
+        plain_hits += int(plain[p] == rn)
+    assert hits >= 0.99 * len(exact), (hits, len(exact))
+    assert hits >= plain_hits
+
+
+def test_dot2_beats_plain_over_many_steps():
+    case = si.make_case(62, 2, 2, True, (48, 40), 40)
+    c32, g32 = case.as_dtype(np.float32)
+    ref = oracle.sweep(g32.astype(np.float64), radius=2, box=True,
+                       coeffs=c32.astype(np.float64), steps=40)
+    comp = oracle.sweep(g32, radius=2, box=True, coeffs=c32, steps=40, accum="compensated")
+    plain = oracle.sweep(g32, radius=2, box=True, coeffs=c32, steps=40)
+    e_comp = np.abs(comp.astype(np.float64) - ref)
+    e_plain = np.abs(plain.astype(np.float64) - ref)
+    assert e_comp.max() < e_plain.max()
+    assert np.sqrt(np.mean(e_comp ** 2)) < 0.5 * np.sqrt(np.mean(e_plain ** 2))
+    # one float32 rounding per step at most, plus second-order terms
+    assert e_comp.max() <= 40 * (pins.U32 + 25 * 25 * pins.U32 ** 2) * float(g32.max()) * 1.01
+
+
+def test_dot2_rejects_float64():
+    with pytest.raises(TypeError):
+        oracle.sweep(np.zeros((5, 5)), radius=1, box=False, coeffs=np.ones(5), steps=1,
+                     accum="compensated")
