@@ -51,6 +51,9 @@ ALU_PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
 ALU_PEAK_PUBLISHED = {"f32": 157.3, "f64": 78.6}
 STENCILS = [(1, False), (2, False), (3, False), (4, False), (1, True), (2, True)]
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_sweep2d_star_r1_f32_16384.json")
+# kernel kinds of the library: (storage dtype, accumulation)
+KINDS = {0: ("f32", "plain"), 1: ("f64", "plain"), 2: ("f32", "compensated")}
+KIND_NAMES = {0: "f32", 1: "f64", 2: "f32c"}
 
 
 def npts(r, box):
@@ -76,14 +79,13 @@ def kernel_source_hash():
 class Problem:
     """Device buffers and a plan for one (stencil, dtype, tuning)."""
 
-    def __init__(self, r, box, dtype, steps=T_STEPS, interior=(N, N), seed=None, **tuning):
+    def __init__(self, r, box, dtype, steps=T_STEPS, interior=(N, N), seed=None, accum="plain",
+                 **tuning):
         import torch
         import paper_2001_01473_amd as s5d
         self.r, self.box, self.dtype, self.steps = r, box, dtype, steps
         seed = si.workload_seed(1) if seed is None else seed
         rng = np.random.default_rng(seed)
-        c = si.random_coeffs(rng, npts(r, box))
-        self.coeffs = c
         c = si.random_coeffs(rng, si.n_points(len(interior), r, box))
         self.coeffs = c
         shape = si.padded_shape(interior, r)
@@ -95,7 +97,7 @@ class Problem:
         self.buf1 = torch.empty_like(self.buf0)
         self.init = self.buf0.clone()
         self.plan = s5d.Plan(ndim=len(interior), radius=r, box=box, dtype=dtype, interior=interior,
-                             steps=steps, coeffs=c, **tuning)
+                             steps=steps, coeffs=c, accum=accum, **tuning)
         self.info = self.plan.query()
         self.cells = int(np.prod(interior))
 
@@ -215,19 +217,20 @@ def full_sweep3d():
     """Every compiled 3D variant at 512^3, T = 1000 (one warm-up, one timed run)."""
     import torch
     from paper_2001_01473_amd import build as lib_build
-    for dtype_code, box, r, cpl, m, nw, bt, nr in lib_build.variants_3d():
-        dtype = "f32" if dtype_code == 0 else "f64"
+    for kind, box, r, cpl, m, nw, bt, nr in lib_build.variants_3d():
+        dtype, accum = KINDS[kind]
         name = "%s3d%dr" % ("box" if box else "star", r)
         try:
             p = Problem(r, bool(box), dtype, interior=(N3, N3, N3), bt=bt, cells_per_lane=cpl,
-                        rows_per_wave=m)
+                        rows_per_wave=m, accum=accum)
         except Exception as e:  # noqa: BLE001 - reported, not fatal
-            print(json.dumps({"stencil": name, "dtype": dtype, "bt": bt, "tile": [nw * m, 64 * cpl],
-                              "error": str(e)[:120]}), flush=True)
+            print(json.dumps({"stencil": name, "kind": KIND_NAMES[kind], "bt": bt,
+                              "tile": [nw * m, 64 * cpl], "error": str(e)[:120]}), flush=True)
             continue
         s = time_steps(p, 1, 1)
         g = N3 ** 3 * T_STEPS / s / 1e9
-        print(json.dumps({"stencil": name, "dtype": dtype, "bt": bt, "tile": [nw * m, 64 * cpl],
+        print(json.dumps({"stencil": name, "kind": KIND_NAMES[kind], "bt": bt,
+                          "tile": [nw * m, 64 * cpl],
                           "stream_chunk": p.info["stream_chunk"], "gcells": round(g, 1)}), flush=True)
         p.close()
         torch.cuda.empty_cache()
@@ -237,21 +240,183 @@ def full_sweep():
     """Every compiled 2D variant at 16384^2, T = 1000 (one warm-up, one timed run)."""
     import torch
     from paper_2001_01473_amd import build as lib_build
-    for dtype_code, box, r, cpl, bt, nr in lib_build.variants_2d():
-        dtype = "f32" if dtype_code == 0 else "f64"
+    for kind, box, r, cpl, bt, nr in lib_build.variants_2d():
+        dtype, accum = KINDS[kind]
         try:
-            p = Problem(r, bool(box), dtype, bt=bt, cells_per_lane=cpl)
+            p = Problem(r, bool(box), dtype, bt=bt, cells_per_lane=cpl, accum=accum)
         except Exception as e:  # noqa: BLE001 - reported, not fatal
-            print(json.dumps({"stencil": stencil_name(r, box), "dtype": dtype, "bt": bt,
+            print(json.dumps({"stencil": stencil_name(r, box), "kind": KIND_NAMES[kind], "bt": bt,
                               "cpl": cpl, "error": str(e)[:120]}), flush=True)
             continue
         s = time_steps(p, 1, 1)
         g = N * N * T_STEPS / s / 1e9
-        print(json.dumps({"stencil": stencil_name(r, box), "dtype": dtype, "bt": bt, "cpl": cpl,
+        print(json.dumps({"stencil": stencil_name(r, box), "kind": KIND_NAMES[kind], "bt": bt,
+                          "cpl": cpl,
                           "stream_chunk": p.info["stream_chunk"], "gcells": round(g, 1)}),
               flush=True)
         p.close()
         torch.cuda.empty_cache()
+
+
+def _device_grid(shape, dtype, seed):
+    """U[0,1) grid generated on the device from `seed` (values are not compared
+    here, only timed)."""
+    import torch
+    td = torch.float32 if dtype == "f32" else torch.float64
+    gen = torch.Generator(device="cuda:0").manual_seed(int(seed) % (1 << 63))
+    return torch.rand(shape, dtype=td, device="cuda:0", generator=gen)
+
+
+def _plan_for(spec, dtype):
+    import paper_2001_01473_amd as s5d
+    rng = np.random.default_rng(spec["seed"])
+    c = si.random_coeffs(rng, si.n_points(spec["ndim"], spec["radius"], spec["box"]))
+    return s5d.Plan(ndim=spec["ndim"], radius=spec["radius"], box=spec["box"], dtype=dtype,
+                    interior=spec["interior"], steps=spec["steps"], coeffs=c)
+
+
+def _timed(fn, reset, reps):
+    """Mean seconds of fn() over reps runs (HIP events on the current stream)."""
+    import torch
+    reset()
+    fn()
+    torch.cuda.synchronize()
+    total = 0.0
+    for _ in range(reps):
+        reset()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        total += a.elapsed_time(b) / 1e3
+    return total / reps
+
+
+def bench_batch(reps=2):
+    """Many-grid workload: 64 independent 2D star grids (sides U{256..4096} per
+    axis, radius 1 or 2, float32, 200 steps).  Batched (one HIP graph) against
+    the same grids run one after the other with s5d_run."""
+    import torch
+    import paper_2001_01473_amd as s5d
+    specs = si.batch_mix(si.workload_seed(3))
+    updates = sum(int(np.prod(s["interior"])) * s["steps"] for s in specs)
+    out = {"workload": "64 2D star grids, sides U{256..4096}, r in {1,2}, f32, T=200",
+           "updates": updates}
+    for dtype in ("f32", "f64"):
+        plans = [_plan_for(s, dtype) for s in specs]
+        b0 = [_device_grid(si.padded_shape(s["interior"], s["radius"]), dtype, s["seed"])
+              for s in specs]
+        b1 = [torch.empty_like(x) for x in b0]
+        init = [x.clone() for x in b0]
+
+        def reset():
+            for x, i in zip(b0, init):
+                x.copy_(i)
+
+        def sequential():
+            for p, x, y in zip(plans, b0, b1):
+                p.run(x, y)
+
+        def sequential_sync():
+            for p, x, y in zip(plans, b0, b1):
+                p.run(x, y)
+                torch.cuda.synchronize()
+
+        res = {"sequential": _timed(sequential, reset, reps),
+               "sequential_sync": _timed(sequential_sync, reset, reps)}
+        if dtype == "f32":
+            for graph in (False, True):
+                batch = s5d.Batch(plans, b0, b1, graph=graph)
+                res["batched_graph" if graph else "batched_eager"] = _timed(batch.run, reset, reps)
+                out["launches_batched"] = batch.query()["launches"]
+                batch.close()
+            out["launches_sequential"] = sum(
+                1 + -(-p.steps // p.query()["bt"]) for p in plans)
+        for k, sec in res.items():
+            out["%s_%s_gcells" % (k, dtype)] = updates / sec / 1e9
+            print("batch %s %s: %.1f GCell/s (%.1f ms)" % (dtype, k, updates / sec / 1e9, sec * 1e3),
+                  file=sys.stderr, flush=True)
+        for p in plans:
+            p.close()
+        del b0, b1, init
+        torch.cuda.empty_cache()
+    out["speedup_vs_sequential_f32"] = (out["batched_graph_f32_gcells"] /
+                                        out["sequential_f32_gcells"])
+    return out
+
+
+def bench_serve(n_requests=32, loads=(0.8,), budgets=(64 << 30,)):
+    """Serving mix: Poisson arrivals of mixed 2D/3D, star/box, r in {1,2},
+    float32/float64 requests with 10..1000 steps.  First the closed-loop
+    capacity (all requests queued at once), then open-loop runs at the given
+    fractions of that capacity; p50/p99 latency = completion - arrival."""
+    import torch
+    import paper_2001_01473_amd as s5d
+    base = si.serve_mix(si.workload_seed(4), n_requests, rate_per_s=1.0)
+    plans = [_plan_for(s, s["dtype"]) for s in base]
+    inits = [_device_grid(si.padded_shape(s["interior"], s["radius"]), s["dtype"], s["seed"])
+             for s in base]
+    updates = [int(np.prod(s["interior"])) * s["steps"] for s in base]
+    out = {"workload": "%d requests: 50%% 2D U{512..8192}^2 / 50%% 3D U{64..256}^3, star/box, "
+                       "r in {1,2}, f32/f64, T U{10..1000}" % n_requests,
+           "updates": sum(updates)}
+
+    def serve(arrivals, budget):
+        srv = s5d.Server(hbm_budget_bytes=budget)
+        t0 = srv.now()
+        order = sorted(range(len(plans)), key=lambda i: arrivals[i])
+        k = 0
+        while True:
+            now = srv.now() - t0
+            while k < len(order) and arrivals[order[k]] <= now:
+                i = order[k]
+                srv.submit(plans[i], inits[i], arrival=t0 + arrivals[i])
+                k += 1
+            running, queued = srv.tick()
+            if running == 0 and queued == 0:
+                if k == len(order):
+                    break
+                time.sleep(max(0.0, min(0.01, arrivals[order[k]] - (srv.now() - t0))))
+        srv.sync()
+        st = srv.stats()
+        srv.close()
+        return st
+
+    # plain: every request alone, one after the other
+    t = time.perf_counter()
+    for p, x in zip(plans, inits):
+        y = torch.empty_like(x)
+        p.run(x.clone(), y)
+        torch.cuda.synchronize()
+    plain = time.perf_counter() - t
+    out["plain_sequential_gcells"] = sum(updates) / plain / 1e9
+    cap = serve([0.0] * len(plans), budgets[0])
+    capacity = cap["updates_done"] / cap["makespan"]
+    out["capacity_gcells"] = capacity / 1e9
+    out["capacity_p50_s"], out["capacity_p99_s"] = cap["latency_p50"], cap["latency_p99"]
+    print("serve capacity %.1f GCell/s, plain %.1f GCell/s" % (capacity / 1e9,
+                                                                 out["plain_sequential_gcells"]),
+          file=sys.stderr, flush=True)
+    mean_upd = float(np.mean(updates))
+    points = []
+    for budget in budgets:
+        for load in loads:
+            rate = load * capacity / mean_upd
+            arrivals = [s["arrival"] / rate for s in base]  # unit-rate arrivals rescaled
+            st = serve(arrivals, budget)
+            points.append({"offered_load": load, "budget_gib": budget / (1 << 30),
+                           "rate_per_s": rate, "throughput_gcells": st["updates_done"] /
+                           st["makespan"] / 1e9, "p50_s": st["latency_p50"],
+                           "p99_s": st["latency_p99"], "ticks": st["ticks"],
+                           "launches": st["launches"], "peak_gib": st["bytes_peak"] / (1 << 30)})
+            print("serve load %.2f budget %.0f GiB: p50 %.3f s p99 %.3f s, %.1f GCell/s" % (
+                load, budget / (1 << 30), st["latency_p50"], st["latency_p99"],
+                points[-1]["throughput_gcells"]), file=sys.stderr, flush=True)
+    out["points"] = points
+    return out
 
 
 def ingest_counters(fetch_dir, write_dir, out_json, out_md, command):
@@ -349,6 +514,14 @@ def main(argv=None):
                     help="time every compiled (stencil, dtype, b_T, cells per lane) at the "
                          "benchmark size and print one JSON line per variant")
     ap.add_argument("--launches", type=int, default=3)
+    ap.add_argument("--batch", action="store_true",
+                    help="also measure the 64-grid batched workload")
+    ap.add_argument("--serve", action="store_true", help="also measure the serving loop")
+    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-loads", default="0.8")
+    ap.add_argument("--serve-budgets-gib", default="64")
+    ap.add_argument("--only-extras", action="store_true",
+                    help="skip the headline sweep; print only the --batch/--serve records")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs of --probe into the traffic record")
     ap.add_argument("--command", default="", help="command line recorded with --ingest-counters")
@@ -375,6 +548,17 @@ def main(argv=None):
         return 0
     if args.full_sweep3d:
         full_sweep3d()
+        return 0
+
+    extras = {}
+    if args.batch:
+        extras["batched"] = bench_batch()
+    if args.serve:
+        extras["serving"] = bench_serve(
+            args.serve_requests, tuple(float(x) for x in args.serve_loads.split(",")),
+            tuple(int(float(x) * (1 << 30)) for x in args.serve_budgets_gib.split(",")))
+    if args.only_extras:
+        print(json.dumps(extras))
         return 0
 
     tuning = {"bt": args.bt} if args.bt else {}
@@ -431,6 +615,7 @@ def main(argv=None):
                 print("bt-curve star2d1r %s bt=%d: %.1f GCell/s" % (dtype, bt, g),
                       file=sys.stderr, flush=True)
         rec["bt_curve_star2d1r"] = curve
+    rec.update(extras)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(1, False, "f32")
     torch.cuda.synchronize()

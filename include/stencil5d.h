@@ -131,6 +131,190 @@ s5d_status s5d_plan_query(const s5d_plan *plan, s5d_tuning *chosen, int64_t *byt
 s5d_status s5d_run(const s5d_plan *plan, void *buf0, void *buf1, void *stream,
                    int32_t *result_index);
 
+/* ---- Performance model and autotuner ----
+ *
+ * The model follows AN5D's "Performance Model": per launch, count the vector
+ * ALU work, the HBM traffic and the LDS traffic of every wave (all lanes
+ * compute every fused level; lanes outside the grid move no data; LDS carries
+ * the 3D edge-row exchange), divide each by the device's rate (VALU 64
+ * lane-operations per clock per CU, HBM 6.0e12 B/s sustained, LDS 128 B per
+ * clock per CU), take the largest and divide by the workgroup-slot
+ * efficiency (the fraction of resident-workgroup slots the launch's waves of
+ * workgroups fill).  The whole sweep is the sum over its rounds. */
+typedef struct s5d_model {
+    uint32_t struct_size; /* = sizeof(s5d_model) */
+    int32_t bound;        /* largest term of the first round's kind: 0 ALU, 1 HBM, 2 LDS */
+    double seconds;       /* predicted time of the whole sweep */
+    double t_alu, t_hbm, t_lds; /* summed over rounds, before the slot efficiency */
+    double eff_cu;        /* slot efficiency of the first (full-depth) round */
+    double hbm_bytes;     /* predicted HBM traffic of the whole sweep */
+    double valu_ops;      /* lane-operations of the whole sweep */
+    int64_t workgroups;   /* workgroups of the first round */
+} s5d_model;
+
+s5d_status s5d_plan_model(const s5d_plan *plan, s5d_model *out);
+
+typedef struct s5d_tune_report {
+    uint32_t struct_size; /* = sizeof(s5d_tune_report) */
+    int32_t n_candidates; /* configurations the model ranked */
+    int32_t n_measured;   /* of which timed on the GPU */
+    int32_t reserved;
+    double model_best_seconds;       /* model time of its top-ranked candidate */
+    double best_seconds_per_step;    /* measured time of the winner (-1 if none measured) */
+    double default_seconds_per_step; /* measured time of the library's default choice */
+} s5d_tune_report;
+
+/* Choose the blocking (b_T, tile, cells per lane, rows per wave, stream block
+ * length h_SN) for `desc` (AN5D "Performance Model" and "Tuning"): enumerate
+ * every compiled variant of the stencil with a ladder of stream block
+ * lengths, rank them by the model, time the best top_k on the GPU (two full
+ * rounds each, on scratch buffers the tuner allocates and frees), and keep
+ * the fastest, or the library's default if none beats it.  top_k = 0 trusts
+ * the model alone.  The winner goes to *best and into the process-wide cache,
+ * from which s5d_plan_create takes it whenever it is given no tuning for a
+ * descriptor with the same stencil, dtype, accumulation and power-of-two
+ * bucket of every extent.  Synchronous on `stream`. */
+s5d_status s5d_autotune(const s5d_desc *desc, int32_t top_k, void *stream, s5d_tuning *best,
+                        s5d_tune_report *report);
+
+/* Write / merge / empty the tuning cache (a small text file, one entry per line). */
+s5d_status s5d_tune_cache_save(const char *path);
+s5d_status s5d_tune_cache_load(const char *path);
+void s5d_tune_cache_clear(void);
+
+/* ---- Batched execution of many independent sweeps ----
+ *
+ * Many grids of uneven sizes (each with its own plan: stencil, extents,
+ * steps, blocking) advance together.  Each grid follows exactly the rounds
+ * s5d_run would give it, so its result is bit-identical to running it alone;
+ * at each round index the rounds of all grids that share a kernel variant
+ * form ONE launch, whose workgroups are spread over the grids by a device
+ * table built at creation.  Small grids thereby share the machine instead of
+ * each under-filling it (AN5D "Execution Model": the thread blocks of a launch
+ * are independent, whichever grid they belong to). */
+typedef struct s5d_batch s5d_batch; /* opaque */
+
+#define S5D_BATCH_GRAPH 1 /* flag: capture the whole sequence into a HIP graph on the
+                             first run and replay it with one graph launch */
+
+/* Build a batch over n grids.  plans[i] (not retained: it may be destroyed
+ * afterwards), buf0[i] and buf1[i] (device pointers, as for s5d_run) describe
+ * grid i; the buffers are bound to the batch, must stay allocated while it
+ * exists, and no two buffers of the batch may overlap.  The device tables are
+ * allocated with hipMalloc on the current device and uploaded synchronously.
+ * Errors: S5D_EINVAL (bad arguments, overlapping buffers), S5D_EUNSUPPORTED,
+ * S5D_ENOMEM, S5D_EDEVICE.  n = 0 gives a batch that does nothing. */
+s5d_status s5d_batch_create(const s5d_plan *const *plans, void *const *buf0, void *const *buf1,
+                            int32_t n, int32_t flags, s5d_batch **out);
+
+/* Enqueue every grid's whole sweep on `stream` (a hipStream_t of the batch's
+ * device; NULL = null stream).  As for s5d_run, buf0[i] must hold grid i's
+ * initial state and result_index (n entries, may be NULL) receives
+ * steps_i % 2.  Asynchronous; a batch may be run again once its inputs have
+ * been reset.  Runs of one batch on different streams must not overlap. */
+s5d_status s5d_batch_run(s5d_batch *batch, void *stream, int32_t *result_index);
+
+/* Launches per run (boundary copies included) and the number of round
+ * indices (may be NULL). */
+s5d_status s5d_batch_query(const s5d_batch *batch, int32_t *n_launches, int32_t *n_round_steps);
+
+/* Wait for the device to drain, then release the batch (NULL accepted). */
+void s5d_batch_destroy(s5d_batch *batch);
+
+/* Create, run on `stream`, synchronise that stream and destroy: a batched
+ * s5d_run for one-off use.  Synchronous. */
+s5d_status s5d_run_batch(const s5d_plan *const *plans, void *const *buf0, void *const *buf1,
+                         int32_t n, void *stream, int32_t *result_index);
+
+/* ---- Serving loop: continuous batching of sweep requests ----
+ *
+ * A server owns a HIP stream and the device memory of the grids it holds.
+ * Requests (a plan and an initial grid) queue in arrival order.  Each call of
+ * s5d_server_tick
+ *   1. admits queued requests in FIFO order while the two buffers of the next
+ *      one fit the HBM budget (and max_running allows it): stream-ordered
+ *      allocation, copy of the initial grid, boundary copy;
+ *   2. advances every running request by one round of its own schedule, all
+ *      of them in one batched launch per kernel variant, so new arrivals join
+ *      at round boundaries and every result is bit-identical to the request
+ *      run alone with s5d_run;
+ *   3. records when requests whose last round was just enqueued complete
+ *      (GPU clock, on the server's time axis).
+ * At most three ticks are in flight: a tick waits for the tick three before
+ * it.  Times are seconds since s5d_server_create on the host's steady clock.
+ * A server is not thread-safe: calls on one server must not overlap. */
+typedef struct s5d_server s5d_server; /* opaque */
+
+typedef struct s5d_server_config {
+    uint32_t struct_size;     /* = sizeof(s5d_server_config) */
+    int32_t max_running;      /* requests running at once; 0 = no limit */
+    int64_t hbm_budget_bytes; /* device memory for the grids of admitted requests */
+} s5d_server_config;
+
+/* Request states. */
+#define S5D_REQ_QUEUED 0
+#define S5D_REQ_RUNNING 1
+#define S5D_REQ_DONE 2     /* finished; result held if it was kept */
+#define S5D_REQ_RELEASED 3 /* result fetched, memory returned */
+
+typedef struct s5d_request_info {
+    uint32_t struct_size; /* = sizeof(s5d_request_info) */
+    int32_t state;        /* S5D_REQ_* */
+    int32_t result_index; /* steps % 2 */
+    int32_t reserved;
+    int64_t updates;      /* interior cells x steps */
+    int64_t rounds_done;  /* rounds enqueued so far */
+    double t_arrival, t_admit, t_done; /* seconds; -1 if not yet */
+} s5d_request_info;
+
+typedef struct s5d_server_stats {
+    uint32_t struct_size; /* = sizeof(s5d_server_stats) */
+    int32_t reserved;
+    int64_t submitted, queued, running, done;
+    int64_t bytes_in_use, bytes_peak; /* grid memory held (both buffers per request) */
+    int64_t ticks, launches;          /* ticks with work, batched launches they made */
+    int64_t updates_done;             /* cell updates of the finished requests */
+    double latency_p50, latency_p99;  /* t_done - t_arrival over finished requests, nearest rank */
+    double makespan;                  /* last completion - first arrival */
+} s5d_server_stats;
+
+/* Create a server on the current device.  Errors: S5D_EINVAL, S5D_ENOMEM,
+ * S5D_EDEVICE. */
+s5d_status s5d_server_create(const s5d_server_config *config, s5d_server **out);
+
+/* Wait for the server's stream, free everything it holds (NULL accepted). */
+void s5d_server_destroy(s5d_server *server);
+
+/* The server clock: seconds since creation. */
+s5d_status s5d_server_now(const s5d_server *server, double *seconds);
+
+/* Queue a request.  The plan is copied (the caller may destroy it).  `init`
+ * (host or device memory, plan's padded grid, boundary included) is read when
+ * the request is admitted, so it must stay valid until the request's state
+ * leaves S5D_REQ_QUEUED.  `arrival` stamps the request on the server clock
+ * (negative: now).  With keep_result != 0 the result stays on the device until
+ * s5d_server_fetch; otherwise it is dropped when the request completes.
+ * S5D_EBUDGET if the request alone exceeds the budget. */
+s5d_status s5d_server_submit(s5d_server *server, const s5d_plan *plan, const void *init,
+                             double arrival, int32_t keep_result, int64_t *id);
+
+/* One tick (see above).  n_running / n_queued (may be NULL) receive the
+ * counts after it. */
+s5d_status s5d_server_tick(s5d_server *server, int32_t *n_running, int32_t *n_queued);
+
+/* Wait for all enqueued work and record the completions. */
+s5d_status s5d_server_sync(s5d_server *server);
+
+/* State and timestamps of one request. */
+s5d_status s5d_server_request(const s5d_server *server, int64_t id, s5d_request_info *info);
+
+/* Copy a finished, kept result into `dst` (host or device memory, one padded
+ * grid) and release the request's buffers.  Synchronous. */
+s5d_status s5d_server_fetch(s5d_server *server, int64_t id, void *dst);
+
+/* Counters, latency percentiles and makespan. */
+s5d_status s5d_server_get_stats(const s5d_server *server, s5d_server_stats *out);
+
 /* Error and norm reductions in float64 between a computed grid and a
  * reference, for checking a sweep against an independent result on the GPU
  * (the relative error measure of the accuracy evaluation).  Over the n

@@ -16,7 +16,8 @@ from . import _lib
 from ._lib import (ACC_COMPENSATED, ACC_PLAIN, BOX, F32, F64, STAR, Stencil5DError,
                    last_error, status_string)
 
-__all__ = ["Plan", "solve", "error_norms", "NORM_NAMES", "Stencil5DError", "status_string",
+__all__ = ["Plan", "Batch", "Server", "solve", "error_norms", "autotune", "tune_cache_save",
+           "tune_cache_load", "tune_cache_clear", "NORM_NAMES", "Stencil5DError", "status_string",
            "last_error",
            "STAR", "BOX", "F32", "F64", "ACC_PLAIN", "ACC_COMPENSATED"]
 
@@ -25,11 +26,13 @@ _TUNING_KEYS = ("bt", "tile0", "tile1", "stream_chunk", "cells_per_lane", "rows_
 
 
 def _dtype_code(dtype):
-    if dtype in (F32, "f32", "float32"):
+    if isinstance(dtype, int) and dtype in (F32, F64):
+        return dtype
+    if dtype in ("f32", "float32"):
         return F32
-    if dtype in (F64, "f64", "float64"):
+    if dtype in ("f64", "float64"):
         return F64
-    name = str(dtype)
+    name = str(getattr(dtype, "__name__", dtype))
     if name.endswith("float32"):
         return F32
     if name.endswith("float64"):
@@ -81,6 +84,15 @@ class Plan:
         out["bytes_per_buffer"] = int(nbytes.value)
         return out
 
+    def model(self) -> dict:
+        """The performance model's prediction for this plan's whole sweep."""
+        m = _lib.S5DModel()
+        m.struct_size = ctypes.sizeof(m)
+        _lib.check(_lib.load().s5d_plan_model(self._h, ctypes.byref(m)), "s5d_plan_model")
+        out = {k: getattr(m, k) for k, _ in m._fields_ if k != "struct_size"}
+        out["bound"] = ("alu", "hbm", "lds")[m.bound]
+        return out
+
     def run(self, buf0, buf1, stream=None) -> int:
         """Enqueue the sweep; returns the index (0/1) of the buffer holding the result."""
         if self._h is None:
@@ -107,6 +119,203 @@ class Plan:
         if getattr(self, "_h", None) is not None:
             _lib.load().s5d_plan_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream_handle(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _check_pair(plan, b0, b1):
+    for b in (b0, b1):
+        if not b.is_cuda or not b.is_contiguous():
+            raise ValueError("buffers must be contiguous device tensors")
+        if tuple(b.shape) != plan.padded_shape:
+            raise ValueError("buffer shape %s != padded shape %s" % (tuple(b.shape), plan.padded_shape))
+        if _dtype_code(b.dtype) != plan.dtype:
+            raise ValueError("buffer dtype does not match the plan")
+
+
+class Batch:
+    """Many independent sweeps run together (``s5d_batch``): per round index,
+    one launch per kernel variant over all grids; optionally replayed as one
+    HIP graph.  ``plans``, ``bufs0`` and ``bufs1`` are equal-length lists; the
+    buffers are bound to the batch and must outlive it."""
+
+    def __init__(self, plans, bufs0, bufs1, *, graph=False):
+        lib = _lib.load()
+        n = len(plans)
+        if not (len(bufs0) == len(bufs1) == n):
+            raise ValueError("plans, bufs0 and bufs1 differ in length")
+        for p, b0, b1 in zip(plans, bufs0, bufs1):
+            _check_pair(p, b0, b1)
+        vp = ctypes.c_void_p
+        self.n = n
+        self._device = bufs0[0].device if n else None
+        self._bufs = (list(bufs0), list(bufs1))  # keep the tensors alive
+        arr = vp * max(n, 1)
+        hp = arr(*[p._h for p in plans])
+        b0 = arr(*[vp(b.data_ptr()) for b in bufs0])
+        b1 = arr(*[vp(b.data_ptr()) for b in bufs1])
+        h = vp()
+        _lib.check(lib.s5d_batch_create(hp, b0, b1, n, _lib.BATCH_GRAPH if graph else 0,
+                                        ctypes.byref(h)), "s5d_batch_create")
+        self._h = h
+
+    def run(self, stream=None):
+        """Enqueue every grid's sweep; returns the list of result buffer indices."""
+        if self._h is None:
+            raise RuntimeError("batch destroyed")
+        idx = (ctypes.c_int32 * max(self.n, 1))()
+        handle = _stream_handle(stream, self._device) if self.n else 0
+        _lib.check(_lib.load().s5d_batch_run(self._h, ctypes.c_void_p(handle), idx), "s5d_batch_run")
+        return [int(idx[i]) for i in range(self.n)]
+
+    def query(self) -> dict:
+        nl, ns = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(_lib.load().s5d_batch_query(self._h, ctypes.byref(nl), ctypes.byref(ns)),
+                   "s5d_batch_query")
+        return {"launches": int(nl.value), "round_steps": int(ns.value)}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.load().s5d_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(*, ndim, radius, box, dtype, interior, steps, coeffs, accum="plain", top_k=4,
+             stream=None):
+    """Model-ranked, GPU-measured choice of the blocking for this problem
+    (``s5d_autotune``); returns (tuning dict, report dict).  The choice is
+    cached for later plans of the same stencil and extent bucket."""
+    lib = _lib.load()
+    desc, keep = _lib.make_desc(ndim, radius, box, _dtype_code(dtype), _accum_code(accum),
+                                interior, steps, coeffs)
+    best = _lib.make_tuning()
+    rep = _lib.S5DTuneReport()
+    rep.struct_size = ctypes.sizeof(rep)
+    handle = _stream_handle(stream, None) if stream is not None else 0
+    st = lib.s5d_autotune(ctypes.byref(desc), int(top_k), ctypes.c_void_p(handle),
+                          ctypes.byref(best), ctypes.byref(rep))
+    del keep
+    _lib.check(st, "s5d_autotune")
+    tun = {k: int(getattr(best, k)) for k in _TUNING_KEYS}
+    report = {k: getattr(rep, k) for k, _ in rep._fields_ if k not in ("struct_size", "reserved")}
+    return tun, report
+
+
+def tune_cache_save(path):
+    _lib.check(_lib.load().s5d_tune_cache_save(str(path).encode()), "s5d_tune_cache_save")
+
+
+def tune_cache_load(path):
+    _lib.check(_lib.load().s5d_tune_cache_load(str(path).encode()), "s5d_tune_cache_load")
+
+
+def tune_cache_clear():
+    _lib.load().s5d_tune_cache_clear()
+
+
+class Server:
+    """Serving loop with continuous batching (``s5d_server``): requests queue,
+    are admitted under an HBM budget and advance one round per ``tick()``,
+    all running requests together.  Times are seconds on the server clock."""
+
+    def __init__(self, *, hbm_budget_bytes, max_running=0):
+        lib = _lib.load()
+        cfg = _lib.S5DServerConfig()
+        cfg.struct_size = ctypes.sizeof(cfg)
+        cfg.max_running = int(max_running)
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        h = ctypes.c_void_p()
+        _lib.check(lib.s5d_server_create(ctypes.byref(cfg), ctypes.byref(h)), "s5d_server_create")
+        self._h = h
+        self._inits = {}  # request id -> initial grid, kept alive until admitted
+
+    def now(self) -> float:
+        t = ctypes.c_double()
+        _lib.check(_lib.load().s5d_server_now(self._h, ctypes.byref(t)), "s5d_server_now")
+        return float(t.value)
+
+    def submit(self, plan, init, *, arrival=-1.0, keep_result=False) -> int:
+        """Queue ``plan`` with initial grid ``init`` (a contiguous host numpy
+        array or device tensor of the plan's padded shape); returns its id."""
+        import numpy as np
+        if hasattr(init, "data_ptr"):
+            if not init.is_contiguous() or tuple(init.shape) != plan.padded_shape:
+                raise ValueError("init must be a contiguous tensor of the padded shape")
+            if _dtype_code(init.dtype) != plan.dtype:
+                raise ValueError("init dtype does not match the plan")
+            ptr = init.data_ptr()
+        else:
+            init = np.ascontiguousarray(init)
+            if init.shape != plan.padded_shape or _dtype_code(init.dtype) != plan.dtype:
+                raise ValueError("init must match the plan's padded shape and dtype")
+            ptr = init.ctypes.data
+        rid = ctypes.c_int64()
+        _lib.check(_lib.load().s5d_server_submit(self._h, plan._h, ctypes.c_void_p(ptr),
+                                                 float(arrival), int(bool(keep_result)),
+                                                 ctypes.byref(rid)), "s5d_server_submit")
+        self._inits[int(rid.value)] = init
+        return int(rid.value)
+
+    def tick(self):
+        """Admit what fits, advance every running request by one round;
+        returns (running, queued)."""
+        nr, nq = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(_lib.load().s5d_server_tick(self._h, ctypes.byref(nr), ctypes.byref(nq)),
+                   "s5d_server_tick")
+        self._drop_admitted()
+        return int(nr.value), int(nq.value)
+
+    def sync(self):
+        _lib.check(_lib.load().s5d_server_sync(self._h), "s5d_server_sync")
+
+    def request(self, rid) -> dict:
+        info = _lib.S5DRequestInfo()
+        info.struct_size = ctypes.sizeof(info)
+        _lib.check(_lib.load().s5d_server_request(self._h, int(rid), ctypes.byref(info)),
+                   "s5d_server_request")
+        return {k: getattr(info, k) for k, _ in info._fields_ if k not in ("struct_size", "reserved")}
+
+    def fetch(self, rid, out):
+        """Copy a finished kept result into ``out`` (tensor or numpy array)."""
+        ptr = out.data_ptr() if hasattr(out, "data_ptr") else out.ctypes.data
+        _lib.check(_lib.load().s5d_server_fetch(self._h, int(rid), ctypes.c_void_p(ptr)),
+                   "s5d_server_fetch")
+        return out
+
+    def stats(self) -> dict:
+        st = _lib.S5DServerStats()
+        st.struct_size = ctypes.sizeof(st)
+        _lib.check(_lib.load().s5d_server_get_stats(self._h, ctypes.byref(st)),
+                   "s5d_server_get_stats")
+        return {k: getattr(st, k) for k, _ in st._fields_ if k not in ("struct_size", "reserved")}
+
+    def _drop_admitted(self):
+        for rid in list(self._inits):
+            if self.request(rid)["state"] != _lib.REQ_QUEUED:
+                del self._inits[rid]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.load().s5d_server_destroy(self._h)
+            self._h = None
+            self._inits.clear()
 
     def __del__(self):
         try:

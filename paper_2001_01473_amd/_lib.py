@@ -24,9 +24,17 @@ ACC_PLAIN, ACC_COMPENSATED = 0, 1
 
 # Every symbol include/stencil5d.h declares.
 EXPORTS = ("s5d_plan_create", "s5d_plan_destroy", "s5d_plan_query", "s5d_run",
+           "s5d_batch_create", "s5d_batch_run", "s5d_batch_query", "s5d_batch_destroy",
+           "s5d_run_batch",
+           "s5d_server_create", "s5d_server_destroy", "s5d_server_now", "s5d_server_submit",
+           "s5d_server_tick", "s5d_server_sync", "s5d_server_request", "s5d_server_fetch",
+           "s5d_server_get_stats",
+           "s5d_plan_model", "s5d_autotune", "s5d_tune_cache_save", "s5d_tune_cache_load",
+           "s5d_tune_cache_clear",
            "s5d_error_norms_workspace_bytes", "s5d_error_norms",
            "s5d_status_string", "s5d_last_error")
 NORMS_COUNT = 5
+BATCH_GRAPH = 1
 
 
 class S5DDesc(ctypes.Structure):
@@ -42,6 +50,48 @@ class S5DTuning(ctypes.Structure):
                 ("tile0", ctypes.c_int32), ("tile1", ctypes.c_int32),
                 ("stream_chunk", ctypes.c_int32), ("cells_per_lane", ctypes.c_int32),
                 ("rows_per_wave", ctypes.c_int32), ("waves_per_eu", ctypes.c_int32)]
+
+
+class S5DServerConfig(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("max_running", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_int64)]
+
+
+class S5DRequestInfo(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("state", ctypes.c_int32),
+                ("result_index", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("updates", ctypes.c_int64), ("rounds_done", ctypes.c_int64),
+                ("t_arrival", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class S5DServerStats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+                ("submitted", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("running", ctypes.c_int64), ("done", ctypes.c_int64),
+                ("bytes_in_use", ctypes.c_int64), ("bytes_peak", ctypes.c_int64),
+                ("ticks", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("updates_done", ctypes.c_int64), ("latency_p50", ctypes.c_double),
+                ("latency_p99", ctypes.c_double), ("makespan", ctypes.c_double)]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_RELEASED = range(4)
+
+
+class S5DModel(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("bound", ctypes.c_int32),
+                ("seconds", ctypes.c_double), ("t_alu", ctypes.c_double),
+                ("t_hbm", ctypes.c_double), ("t_lds", ctypes.c_double),
+                ("eff_cu", ctypes.c_double), ("hbm_bytes", ctypes.c_double),
+                ("valu_ops", ctypes.c_double), ("workgroups", ctypes.c_int64)]
+
+
+class S5DTuneReport(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("n_candidates", ctypes.c_int32),
+                ("n_measured", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("model_best_seconds", ctypes.c_double),
+                ("best_seconds_per_step", ctypes.c_double),
+                ("default_seconds_per_step", ctypes.c_double)]
 
 
 class Stencil5DError(RuntimeError):
@@ -63,6 +113,13 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libstencil5d.so is not built (%s); run "
                                "`python -m paper_2001_01473_amd.build`" % LIB_PATH)
+        # One HIP runtime per process: PyTorch ships its own libamdhip64.so.7
+        # and the library binds to whichever copy is loaded first, so torch
+        # (which provides the device memory and streams) is loaded before it.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         vp = ctypes.c_void_p
         lib.s5d_plan_create.restype = ctypes.c_int32
@@ -75,6 +132,49 @@ def load():
                                        ctypes.POINTER(ctypes.c_int64)]
         lib.s5d_run.restype = ctypes.c_int32
         lib.s5d_run.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int32)]
+        vpp = ctypes.POINTER(vp)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        lib.s5d_batch_create.restype = ctypes.c_int32
+        lib.s5d_batch_create.argtypes = [vpp, vpp, vpp, ctypes.c_int32, ctypes.c_int32, vpp]
+        lib.s5d_batch_run.restype = ctypes.c_int32
+        lib.s5d_batch_run.argtypes = [vp, vp, i32p]
+        lib.s5d_batch_query.restype = ctypes.c_int32
+        lib.s5d_batch_query.argtypes = [vp, i32p, i32p]
+        lib.s5d_batch_destroy.restype = None
+        lib.s5d_batch_destroy.argtypes = [vp]
+        lib.s5d_run_batch.restype = ctypes.c_int32
+        lib.s5d_run_batch.argtypes = [vpp, vpp, vpp, ctypes.c_int32, vp, i32p]
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.s5d_server_create.restype = ctypes.c_int32
+        lib.s5d_server_create.argtypes = [ctypes.POINTER(S5DServerConfig), vpp]
+        lib.s5d_server_destroy.restype = None
+        lib.s5d_server_destroy.argtypes = [vp]
+        lib.s5d_server_now.restype = ctypes.c_int32
+        lib.s5d_server_now.argtypes = [vp, dp]
+        lib.s5d_server_submit.restype = ctypes.c_int32
+        lib.s5d_server_submit.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int32, i64p]
+        lib.s5d_server_tick.restype = ctypes.c_int32
+        lib.s5d_server_tick.argtypes = [vp, i32p, i32p]
+        lib.s5d_server_sync.restype = ctypes.c_int32
+        lib.s5d_server_sync.argtypes = [vp]
+        lib.s5d_server_request.restype = ctypes.c_int32
+        lib.s5d_server_request.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(S5DRequestInfo)]
+        lib.s5d_server_fetch.restype = ctypes.c_int32
+        lib.s5d_server_fetch.argtypes = [vp, ctypes.c_int64, vp]
+        lib.s5d_server_get_stats.restype = ctypes.c_int32
+        lib.s5d_server_get_stats.argtypes = [vp, ctypes.POINTER(S5DServerStats)]
+        lib.s5d_plan_model.restype = ctypes.c_int32
+        lib.s5d_plan_model.argtypes = [vp, ctypes.POINTER(S5DModel)]
+        lib.s5d_autotune.restype = ctypes.c_int32
+        lib.s5d_autotune.argtypes = [ctypes.POINTER(S5DDesc), ctypes.c_int32, vp,
+                                     ctypes.POINTER(S5DTuning), ctypes.POINTER(S5DTuneReport)]
+        lib.s5d_tune_cache_save.restype = ctypes.c_int32
+        lib.s5d_tune_cache_save.argtypes = [ctypes.c_char_p]
+        lib.s5d_tune_cache_load.restype = ctypes.c_int32
+        lib.s5d_tune_cache_load.argtypes = [ctypes.c_char_p]
+        lib.s5d_tune_cache_clear.restype = None
+        lib.s5d_tune_cache_clear.argtypes = []
         lib.s5d_error_norms_workspace_bytes.restype = ctypes.c_int64
         lib.s5d_error_norms_workspace_bytes.argtypes = [ctypes.c_int64]
         lib.s5d_error_norms.restype = ctypes.c_int32

@@ -41,9 +41,9 @@ DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                 "-I" + CSRC, "-I" + INCLUDE]
 
-HOST_SOURCES = ["abi.cpp", "halo.hip", "norms.hip"]
+HOST_SOURCES = ["abi.cpp", "batch.cpp", "server.cpp", "tune.cpp", "halo.hip", "norms.hip"]
 HEADERS = ["s5d_internal.h", "kcommon.h", "sweep2d.h", "sweep3d.h"]
-HOST_HEADERS = ["norms.h"]  # included by host sources only
+HOST_HEADERS = ["host.h", "batch.h", "norms.h"]  # included by host sources only
 
 # Kernel kinds: (name, C++ type, 32-bit words per element, accumulation
 # policy).  Kind 2 is float32 with compensated (Dot2) accumulation.
@@ -170,7 +170,9 @@ _RES_KEYS = {"VGPRs": "vgprs", "AGPRs": "agprs", "ScratchSize [bytes/lane]": "sc
 
 
 def _parse_resources(text):
-    """Kernel resource remarks of one compile (one kernel per unit)."""
+    """Kernel resource remarks of one compile.  A unit holds a variant's
+    single-grid and batched kernels; the worse value of the two is kept
+    (the largest register, scratch and LDS use, the lowest occupancy)."""
     import re
     out = {}
     for line in text.splitlines():
@@ -178,7 +180,11 @@ def _parse_resources(text):
                       r"Occupancy \[waves/SIMD\]|LDS Size \[bytes/block\]): (\d+) \[-Rpass-analysis",
                       line)
         if m:
-            out[_RES_KEYS[m.group(1)]] = int(m.group(2))
+            key, val = _RES_KEYS[m.group(1)], int(m.group(2))
+            if key not in out:
+                out[key] = val
+            else:
+                out[key] = min(out[key], val) if key == "occupancy" else max(out[key], val)
     return out
 
 
@@ -257,7 +263,7 @@ def _compile(src, header_digest, incremental):
     """Compile one unit; returns (object path, seconds, kernel resources)."""
     import json
     base = os.path.splitext(os.path.basename(src))[0]
-    key = _digest([src], DEVICE_FLAGS + [header_digest, "v6"])
+    key = _digest([src], DEVICE_FLAGS + [header_digest, "v7"])
     obj = os.path.join(BUILD, "obj", "%s.%s.o" % (base, key))
     meta = obj + ".res.json"
     if incremental and os.path.exists(obj) and os.path.exists(meta):
@@ -293,13 +299,15 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
     cands = [v for v in candidates_2d() if only is None or re.search(only, _vname(v))]
     cands3 = [v for v in candidates_3d() if only is None or re.search(only, _vname3(v))]
     units, _ = _generate(cands, cands3)
-    hdr = _digest([os.path.join(CSRC, h) for h in HEADERS] +
-                  [os.path.join(INCLUDE, "stencil5d.h")], [])
+    # kernel units include only the device headers; host sources also the
+    # public header and the host-side internal headers
+    hdr = _digest([os.path.join(CSRC, h) for h in HEADERS], [])
     jobs = jobs or max(1, min(32, os.cpu_count() or 1))
     t0 = time.time()
     objs, res_by_unit = {}, {}
     host = [os.path.join(CSRC, s) for s in HOST_SOURCES]
-    host_hdr = hdr + _digest([os.path.join(CSRC, h) for h in HOST_HEADERS], [])
+    host_hdr = hdr + _digest([os.path.join(CSRC, h) for h in HOST_HEADERS] +
+                             [os.path.join(INCLUDE, "stencil5d.h")], [])
     # longest first: the box and deep variants dominate the build time
     order = sorted(units, key=lambda p: (("box" not in p), -len(p))) + host
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

@@ -12,9 +12,8 @@
 #include <string>
 #include <vector>
 
+#include "host.h"
 #include "norms.h"
-#include "s5d_internal.h"
-#include "stencil5d.h"
 
 using s5d::Entry2D;
 using s5d::Entry3D;
@@ -28,6 +27,10 @@ namespace {
 
 thread_local std::string g_last_error;
 
+}  // namespace
+
+namespace s5d {
+
 s5d_status fail(s5d_status st, const std::string& msg) {
   g_last_error = msg;
   return st;
@@ -36,6 +39,15 @@ s5d_status fail(s5d_status st, const std::string& msg) {
 s5d_status device_fail(hipError_t e, const char* what) {
   return fail(S5D_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
+
+void clear_error() { g_last_error.clear(); }
+
+}  // namespace s5d
+
+using s5d::device_fail;
+using s5d::fail;
+
+namespace {
 
 // Largest radius with kernels, per dimensionality and shape.
 int max_radius(int ndim, int shape) {
@@ -185,18 +197,6 @@ RoundSchedule schedule_rounds(int64_t T, int bt) {
 
 }  // namespace
 
-struct s5d_plan {
-  s5d_desc d;
-  std::vector<double> coeffs;
-  s5d_tuning tun;
-  int64_t padded[3];
-  int64_t bytes;
-  int elem;
-  int kind;             // kernel kind: KIND_F32, KIND_F64 or KIND_F32_COMP
-  Kernel2D by_bt[16];   // 2D: index bt -> kernel for a round of bt steps (same tile)
-  Kernel3D by_bt3[16];  // 3D: likewise
-};
-
 namespace {
 
 s5d_status plan_2d(s5d_plan* p, const s5d_tuning& req, int box, int r) {
@@ -309,6 +309,73 @@ s5d_status plan_3d(s5d_plan* p, const s5d_tuning& req, int box, int r) {
 
 }  // namespace
 
+namespace s5d {
+
+std::vector<int> plan_rounds(const s5d_plan* p) {
+  const RoundSchedule rs = schedule_rounds(p->d.steps, p->tun.bt);
+  std::vector<int> out;
+  out.reserve(static_cast<size_t>(rs.total()));
+  for (int64_t i = 0; i < rs.n_full; ++i) out.push_back(rs.bt);
+  for (int i = 0; i < rs.n_tail; ++i) out.push_back(rs.tail[i]);
+  return out;
+}
+
+namespace {
+Round2D round2d(const s5d_plan* p, const void* src, void* dst, hipStream_t stream) {
+  Round2D rd;
+  rd.src = src;
+  rd.dst = dst;
+  rd.I0 = static_cast<int32_t>(p->d.interior[0]);
+  rd.I1 = static_cast<int32_t>(p->d.interior[1]);
+  rd.chunk = p->tun.stream_chunk;
+  rd.coeffs = p->coeffs.data();
+  rd.stream = stream;
+  return rd;
+}
+Round3D round3d(const s5d_plan* p, const void* src, void* dst, hipStream_t stream) {
+  Round3D rd;
+  rd.src = src;
+  rd.dst = dst;
+  rd.I0 = static_cast<int32_t>(p->d.interior[0]);
+  rd.I1 = static_cast<int32_t>(p->d.interior[1]);
+  rd.I2 = static_cast<int32_t>(p->d.interior[2]);
+  rd.chunk = p->tun.stream_chunk;
+  rd.coeffs = p->coeffs.data();
+  rd.stream = stream;
+  return rd;
+}
+}  // namespace
+
+hipError_t launch_round(const s5d_plan* p, int bt, const void* src, void* dst, hipStream_t stream) {
+  if (p->d.ndim == 3) return p->by_bt3[bt].launch(round3d(p, src, dst, stream));
+  return p->by_bt[bt].launch(round2d(p, src, dst, stream));
+}
+
+BatchHooks batch_hooks(const s5d_plan* p, int bt) {
+  if (p->d.ndim == 3) return BatchHooks{p->by_bt3[bt].launch_batch, p->by_bt3[bt].item_bytes};
+  return BatchHooks{p->by_bt[bt].launch_batch, p->by_bt[bt].item_bytes};
+}
+
+int fill_round_item(const s5d_plan* p, int bt, const void* src, void* dst, void* item) {
+  if (p->d.ndim == 3) return p->by_bt3[bt].fill_item(item, round3d(p, src, dst, nullptr));
+  return p->by_bt[bt].fill_item(item, round2d(p, src, dst, nullptr));
+}
+
+hipError_t launch_boundary_copy(const s5d_plan* p, const void* buf0, void* buf1, hipStream_t stream) {
+  return launch_halo_copy(buf0, buf1, p->elem, p->d.ndim, p->padded, p->d.radius, stream);
+}
+
+s5d_status check_buffers(const s5d_plan* p, const void* buf0, const void* buf1) {
+  if (!buf0 || !buf1) return fail(S5D_EINVAL, "buffer pointer is NULL");
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(buf0), a1 = reinterpret_cast<uintptr_t>(buf1);
+  const uintptr_t nb = static_cast<uintptr_t>(p->bytes);
+  if (a0 < a1 + nb && a1 < a0 + nb) return fail(S5D_EINVAL, "buffers overlap");
+  if (a0 % p->elem != 0 || a1 % p->elem != 0) return fail(S5D_EINVAL, "buffers not aligned to the element size");
+  return S5D_OK;
+}
+
+}  // namespace s5d
+
 extern "C" {
 
 const char* s5d_status_string(s5d_status status) {
@@ -396,13 +463,27 @@ s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_p
   p->elem = d.dtype == S5D_F32 ? 4 : 8;
   p->kind = d.accum == S5D_ACC_COMPENSATED ? KIND_F32_COMP : d.dtype == S5D_F32 ? KIND_F32 : KIND_F64;
   p->bytes = total * p->elem;
-  for (int b = 0; b < 16; ++b) {
-    p->by_bt[b] = Kernel2D{nullptr, nullptr, 0, 0, 0};
-    p->by_bt3[b] = Kernel3D{nullptr, nullptr, 0, 0, 0, 0};
+  auto reset = [&]() {
+    for (int b = 0; b < 16; ++b) {
+      p->by_bt[b] = Kernel2D{};
+      p->by_bt3[b] = Kernel3D{};
+    }
+    std::memset(&p->tun, 0, sizeof(p->tun));
+    p->tun.struct_size = sizeof(s5d_tuning);
+  };
+  reset();
+  // without a tuning, an autotuned choice for this stencil and extent bucket
+  // is taken if one is cached and still valid; else the library's defaults
+  s5d_tuning cached;
+  s5d_status st = S5D_EINVAL;
+  if (!tuning && s5d::tune_cache_lookup(d, &cached)) {
+    st = d.ndim == 2 ? plan_2d(p, cached, box, r) : plan_3d(p, cached, box, r);
+    if (st != S5D_OK) {
+      g_last_error.clear();
+      reset();
+    }
   }
-  std::memset(&p->tun, 0, sizeof(p->tun));
-  p->tun.struct_size = sizeof(s5d_tuning);
-  const s5d_status st = d.ndim == 2 ? plan_2d(p, req, box, r) : plan_3d(p, req, box, r);
+  if (st != S5D_OK) st = d.ndim == 2 ? plan_2d(p, req, box, r) : plan_3d(p, req, box, r);
   if (st != S5D_OK) {
     delete p;
     return st;
@@ -427,64 +508,19 @@ s5d_status s5d_plan_query(const s5d_plan* plan, s5d_tuning* chosen, int64_t* byt
 s5d_status s5d_run(const s5d_plan* plan, void* buf0, void* buf1, void* stream, int32_t* result_index) {
   g_last_error.clear();
   if (!plan) return fail(S5D_EINVAL, "plan is NULL");
-  if (!buf0 || !buf1) return fail(S5D_EINVAL, "buffer pointer is NULL");
-  const uintptr_t a0 = reinterpret_cast<uintptr_t>(buf0), a1 = reinterpret_cast<uintptr_t>(buf1);
-  const uintptr_t nb = static_cast<uintptr_t>(plan->bytes);
-  if (a0 < a1 + nb && a1 < a0 + nb) return fail(S5D_EINVAL, "buffers overlap");
-  if (a0 % plan->elem != 0 || a1 % plan->elem != 0) return fail(S5D_EINVAL, "buffers not aligned to the element size");
+  const s5d_status bst = s5d::check_buffers(plan, buf0, buf1);
+  if (bst != S5D_OK) return bst;
   const int64_t T = plan->d.steps;
   if (result_index) *result_index = static_cast<int32_t>(T % 2);
   if (T == 0) return S5D_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   (void)hipGetLastError();
-  hipError_t e = s5d::launch_halo_copy(buf0, buf1, plan->elem, plan->d.ndim, plan->padded, plan->d.radius, st);
+  hipError_t e = s5d::launch_boundary_copy(plan, buf0, buf1, st);
   if (e != hipSuccess) return device_fail(e, "boundary copy launch");
-
-  const RoundSchedule rs = schedule_rounds(T, plan->tun.bt);
   void* bufs[2] = {buf0, buf1};
-  int64_t k = 0;
-  if (plan->d.ndim == 3) {
-    s5d::Round3D rd;
-    rd.I0 = static_cast<int32_t>(plan->d.interior[0]);
-    rd.I1 = static_cast<int32_t>(plan->d.interior[1]);
-    rd.I2 = static_cast<int32_t>(plan->d.interior[2]);
-    rd.chunk = plan->tun.stream_chunk;
-    rd.coeffs = plan->coeffs.data();
-    rd.stream = st;
-    auto one3 = [&](int bt) -> hipError_t {
-      rd.src = bufs[k % 2];
-      rd.dst = bufs[(k + 1) % 2];
-      ++k;
-      return plan->by_bt3[bt].launch(rd);
-    };
-    for (int64_t i = 0; i < rs.n_full; ++i) {
-      e = one3(rs.bt);
-      if (e != hipSuccess) return device_fail(e, "sweep launch");
-    }
-    for (int i = 0; i < rs.n_tail; ++i) {
-      e = one3(rs.tail[i]);
-      if (e != hipSuccess) return device_fail(e, "sweep launch");
-    }
-    return S5D_OK;
-  }
-  s5d::Round2D rd;
-  rd.I0 = static_cast<int32_t>(plan->d.interior[0]);
-  rd.I1 = static_cast<int32_t>(plan->d.interior[1]);
-  rd.chunk = plan->tun.stream_chunk;
-  rd.coeffs = plan->coeffs.data();
-  rd.stream = st;
-  auto one = [&](int bt) -> hipError_t {
-    rd.src = bufs[k % 2];
-    rd.dst = bufs[(k + 1) % 2];
-    ++k;
-    return plan->by_bt[bt].launch(rd);
-  };
-  for (int64_t i = 0; i < rs.n_full; ++i) {
-    e = one(rs.bt);
-    if (e != hipSuccess) return device_fail(e, "sweep launch");
-  }
-  for (int i = 0; i < rs.n_tail; ++i) {
-    e = one(rs.tail[i]);
+  const std::vector<int> rounds = s5d::plan_rounds(plan);
+  for (size_t k = 0; k < rounds.size(); ++k) {
+    e = s5d::launch_round(plan, rounds[k], bufs[k % 2], bufs[(k + 1) % 2], st);
     if (e != hipSuccess) return device_fail(e, "sweep launch");
   }
   return S5D_OK;

@@ -1,0 +1,43 @@
+// Grouped launches of many grids' rounds (batch.cpp), shared by the batch
+// executor and the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <utility>
+#include <vector>
+
+#include "host.h"
+
+namespace s5d {
+
+// One round of one grid: bt fused steps of `plan` from src into dst.
+struct RoundItem {
+  const s5d_plan* plan;
+  int bt;
+  const void* src;
+  void* dst;
+};
+
+// One batched launch: the kernel variant, and the byte offsets of its items
+// and of its workgroup map inside the device table.
+struct GroupLaunch {
+  LaunchBatchFn fn;
+  size_t items_off;
+  size_t map_off;
+  int nblocks;
+};
+
+// Lay out the items and workgroup maps of one round step in `blob` (host
+// copy of the device table), one GroupLaunch per kernel variant.
+s5d_status build_step(const std::vector<RoundItem>& items, std::vector<unsigned char>& blob,
+                      std::vector<GroupLaunch>& out);
+
+// Enqueue the launches of a step whose table was uploaded to `dev`.
+hipError_t enqueue_step(const std::vector<GroupLaunch>& launches, const unsigned char* dev, hipStream_t stream);
+
+// EINVAL if any two [begin, end) byte ranges overlap.
+s5d_status check_disjoint(const std::vector<std::pair<uintptr_t, uintptr_t>>& ranges);
+
+}  // namespace s5d

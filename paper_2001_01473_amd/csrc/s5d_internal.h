@@ -43,12 +43,27 @@ struct Sweep2DArgs {
 using Launch2DFn = hipError_t (*)(const Round2D&);
 using Occupancy2DFn = int (*)();   // resident workgroups per CU (0 if unknown)
 
+// Batched launches: one launch runs a round of many grids that share a kernel
+// variant.  The host writes one item per grid (its launch geometry and its
+// coefficients in the variant's layout, item_bytes each) and one BlockMap
+// entry per workgroup of the launch: which item, and which workgroup of that
+// grid's own launch it stands for.
+struct BlockMap {
+  int32_t item;
+  int32_t block;
+};
+using FillItem2DFn = int (*)(void* item, const Round2D& rd);  // returns the grid's workgroups
+using LaunchBatchFn = hipError_t (*)(const void* items, const BlockMap* map, int nblocks, hipStream_t stream);
+
 struct Kernel2D {
   Launch2DFn launch;
   Occupancy2DFn occupancy;
   int cpl;       // cells per lane
   int bt;        // fused time steps
   int tile;      // 64 * cpl
+  FillItem2DFn fill_item;
+  LaunchBatchFn launch_batch;
+  int item_bytes;
 };
 
 // One compiled 2D kernel variant.  The build enumerates the variants (one
@@ -86,6 +101,7 @@ struct Sweep3DArgs {
 };
 
 using Launch3DFn = hipError_t (*)(const Round3D&);
+using FillItem3DFn = int (*)(void* item, const Round3D& rd);
 
 struct Kernel3D {
   Launch3DFn launch;
@@ -94,6 +110,9 @@ struct Kernel3D {
   int m;                    // rows per wave along axis 1
   int nw;                   // waves per workgroup (tile rows = nw * m)
   int bt;
+  FillItem3DFn fill_item;
+  LaunchBatchFn launch_batch;
+  int item_bytes;
 };
 
 struct Entry3D {

@@ -1,0 +1,425 @@
+// Serving loop: continuous batching of independent sweep requests.
+//
+// Requests (a plan and an initial grid) queue in arrival order.  Each tick
+//  1. admits queued requests in FIFO order while their two device buffers fit
+//     the HBM budget (stream-ordered allocation, initial copy, boundary copy);
+//  2. advances EVERY running request by one round of its own schedule (the
+//     rounds s5d_run would give it, so every result is bit-identical to the
+//     request run alone), all of them in one batched launch per kernel
+//     variant, through a device table uploaded from pinned staging;
+//  3. records an event; requests whose last round is in this tick complete
+//     when it fires, and their completion time is read from the GPU clock.
+// New arrivals therefore join at round boundaries, and grids stay resident in
+// HBM from admission to completion.  At most kSlots ticks are in flight: the
+// host prepares the next tick while the GPU runs the previous ones.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+#include "batch.h"
+#include "host.h"
+
+namespace {
+
+constexpr int kSlots = 3;
+
+struct Request {
+  int64_t id = 0;
+  s5d_plan plan;
+  const void* init = nullptr;
+  bool keep = false;
+  int32_t state = S5D_REQ_QUEUED;
+  double t_arrival = 0, t_admit = -1, t_done = -1;
+  std::vector<int> rounds;
+  size_t next = 0;
+  void* buf[2] = {nullptr, nullptr};
+  int64_t bytes2 = 0;  // both buffers
+  int64_t updates = 0;
+};
+
+struct Slot {
+  unsigned char* host = nullptr;  // pinned staging
+  unsigned char* dev = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+};
+
+struct Finishing {
+  hipEvent_t ev;
+  std::vector<Request*> reqs;
+};
+
+}  // namespace
+
+struct s5d_server {
+  s5d_server_config cfg;
+  hipStream_t stream = nullptr;
+  hipEvent_t base = nullptr;
+  std::chrono::steady_clock::time_point t0;
+  std::unordered_map<int64_t, std::unique_ptr<Request>> reqs;
+  std::deque<Request*> queue;
+  std::vector<Request*> running;
+  std::deque<Finishing> finishing;
+  std::vector<hipEvent_t> event_pool;
+  Slot slots[kSlots];
+  int64_t next_id = 1;
+  int64_t used = 0, peak = 0;
+  int64_t ticks = 0, launches = 0, done = 0, updates_done = 0;
+  double first_arrival = -1, last_done = -1;
+  std::vector<double> latencies;
+};
+
+using s5d::device_fail;
+using s5d::fail;
+
+namespace {
+
+double host_now(const s5d_server* s) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t0).count();
+}
+
+s5d_status take_event(s5d_server* s, hipEvent_t* ev) {
+  if (!s->event_pool.empty()) {
+    *ev = s->event_pool.back();
+    s->event_pool.pop_back();
+    return S5D_OK;
+  }
+  const hipError_t e = hipEventCreate(ev);
+  return e == hipSuccess ? S5D_OK : device_fail(e, "hipEventCreate");
+}
+
+void release_buffers(s5d_server* s, Request* r) {
+  for (void*& b : r->buf) {
+    if (b) (void)hipFreeAsync(b, s->stream);  // stream-ordered: after the request's last use
+    b = nullptr;
+  }
+  s->used -= r->bytes2;
+}
+
+// Move requests whose completion event has fired to DONE.
+s5d_status retire(s5d_server* s) {
+  while (!s->finishing.empty()) {
+    Finishing& f = s->finishing.front();
+    const hipError_t q = hipEventQuery(f.ev);
+    if (q == hipErrorNotReady) break;
+    if (q != hipSuccess) return device_fail(q, "hipEventQuery");
+    float ms = 0.f;
+    const hipError_t e = hipEventElapsedTime(&ms, s->base, f.ev);
+    const double t = e == hipSuccess ? ms * 1e-3 : host_now(s);
+    for (Request* r : f.reqs) {
+      r->t_done = t;
+      r->state = S5D_REQ_DONE;
+      ++s->done;
+      s->updates_done += r->updates;
+      s->latencies.push_back(t - r->t_arrival);
+      s->last_done = std::max(s->last_done, t);
+    }
+    s->event_pool.push_back(f.ev);
+    s->finishing.pop_front();
+  }
+  return S5D_OK;
+}
+
+s5d_status admit(s5d_server* s, Request* r) {
+  const int64_t nb = r->plan.bytes;
+  for (int i = 0; i < 2; ++i) {
+    const hipError_t e = hipMallocAsync(&r->buf[i], static_cast<size_t>(nb), s->stream);
+    if (e != hipSuccess) {
+      r->buf[i] = nullptr;
+      if (i == 1) {
+        (void)hipFreeAsync(r->buf[0], s->stream);
+        r->buf[0] = nullptr;
+      }
+      return device_fail(e, "hipMallocAsync");
+    }
+  }
+  hipError_t e = hipMemcpyAsync(r->buf[0], r->init, static_cast<size_t>(nb), hipMemcpyDefault, s->stream);
+  if (e != hipSuccess) return device_fail(e, "initial copy");
+  r->init = nullptr;
+  r->rounds = s5d::plan_rounds(&r->plan);
+  if (!r->rounds.empty()) {
+    e = s5d::launch_boundary_copy(&r->plan, r->buf[0], r->buf[1], s->stream);
+    if (e != hipSuccess) return device_fail(e, "boundary copy launch");
+  }
+  r->state = S5D_REQ_RUNNING;
+  r->t_admit = host_now(s);
+  return S5D_OK;
+}
+
+s5d_status grow_slot(Slot& sl, size_t need) {
+  if (need <= sl.cap) return S5D_OK;
+  size_t cap = std::max<size_t>(need, 2 * sl.cap);
+  cap = std::max<size_t>(cap, 1 << 16);
+  if (sl.pending) (void)hipEventSynchronize(sl.ev);
+  if (sl.host) (void)hipHostFree(sl.host);
+  if (sl.dev) (void)hipFree(sl.dev);
+  sl.host = nullptr;
+  sl.dev = nullptr;
+  sl.cap = 0;
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&sl.host), cap, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    sl.host = nullptr;
+    return device_fail(e, "hipHostMalloc of the tick table");
+  }
+  e = hipMalloc(reinterpret_cast<void**>(&sl.dev), cap);
+  if (e != hipSuccess) {
+    sl.dev = nullptr;
+    return device_fail(e, "hipMalloc of the tick table");
+  }
+  sl.cap = cap;
+  return S5D_OK;
+}
+
+void destroy_server(s5d_server* s) {
+  if (!s) return;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  for (auto& kv : s->reqs)
+    for (void* b : kv.second->buf)
+      if (b) (void)hipFreeAsync(b, s->stream);
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  for (Slot& sl : s->slots) {
+    if (sl.host) (void)hipHostFree(sl.host);
+    if (sl.dev) (void)hipFree(sl.dev);
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
+  }
+  for (Finishing& f : s->finishing) (void)hipEventDestroy(f.ev);
+  for (hipEvent_t ev : s->event_pool) (void)hipEventDestroy(ev);
+  if (s->base) (void)hipEventDestroy(s->base);
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  (void)hipGetLastError();
+  delete s;
+}
+
+double percentile(std::vector<double> v, double q) {
+  if (v.empty()) return 0.0;
+  std::sort(v.begin(), v.end());
+  // nearest rank
+  size_t k = static_cast<size_t>(std::ceil(q * static_cast<double>(v.size())));
+  k = std::min(std::max<size_t>(k, 1), v.size());
+  return v[k - 1];
+}
+
+}  // namespace
+
+extern "C" {
+
+s5d_status s5d_server_create(const s5d_server_config* config, s5d_server** out) {
+  s5d::clear_error();
+  if (!out) return fail(S5D_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!config) return fail(S5D_EINVAL, "config is NULL");
+  if (config->struct_size < sizeof(s5d_server_config)) return fail(S5D_EINVAL, "config->struct_size too small");
+  if (config->hbm_budget_bytes <= 0) return fail(S5D_EINVAL, "hbm_budget_bytes must be > 0");
+  if (config->max_running < 0) return fail(S5D_EINVAL, "max_running must be >= 0");
+  s5d_server* s = new (std::nothrow) s5d_server;
+  if (!s) return fail(S5D_ENOMEM, "server allocation failed");
+  s->cfg = *config;
+  hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    s->stream = nullptr;
+    destroy_server(s);
+    return device_fail(e, "server stream");
+  }
+  for (Slot& sl : s->slots) {
+    e = hipEventCreate(&sl.ev);
+    if (e != hipSuccess) {
+      sl.ev = nullptr;
+      destroy_server(s);
+      return device_fail(e, "hipEventCreate");
+    }
+  }
+  e = hipEventCreate(&s->base);
+  if (e == hipSuccess) e = hipEventRecord(s->base, s->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(s->base);
+  if (e != hipSuccess) {
+    destroy_server(s);
+    return device_fail(e, "server clock");
+  }
+  s->t0 = std::chrono::steady_clock::now();
+  *out = s;
+  return S5D_OK;
+}
+
+void s5d_server_destroy(s5d_server* server) { destroy_server(server); }
+
+s5d_status s5d_server_now(const s5d_server* server, double* seconds) {
+  if (!server || !seconds) return fail(S5D_EINVAL, "server and seconds must not be NULL");
+  *seconds = host_now(server);
+  return S5D_OK;
+}
+
+s5d_status s5d_server_submit(s5d_server* s, const s5d_plan* plan, const void* init, double arrival,
+                             int32_t keep_result, int64_t* id) {
+  s5d::clear_error();
+  if (!s || !plan || !init) return fail(S5D_EINVAL, "server, plan and init must not be NULL");
+  const int64_t bytes2 = 2 * plan->bytes;
+  if (bytes2 > s->cfg.hbm_budget_bytes) return fail(S5D_EBUDGET, "request larger than the HBM budget");
+  std::unique_ptr<Request> r(new (std::nothrow) Request);
+  if (!r) return fail(S5D_ENOMEM, "request allocation failed");
+  try {
+    r->plan = *plan;
+  } catch (...) {
+    return fail(S5D_ENOMEM, "plan copy failed");
+  }
+  r->id = s->next_id++;
+  r->init = init;
+  r->keep = keep_result != 0;
+  r->t_arrival = arrival >= 0 ? arrival : host_now(s);
+  r->bytes2 = bytes2;
+  r->updates = plan->d.steps * plan->d.interior[0] * plan->d.interior[1] *
+               (plan->d.ndim == 3 ? plan->d.interior[2] : 1);
+  if (s->first_arrival < 0 || r->t_arrival < s->first_arrival) s->first_arrival = r->t_arrival;
+  Request* raw = r.get();
+  s->reqs[raw->id] = std::move(r);
+  s->queue.push_back(raw);
+  if (id) *id = raw->id;
+  return S5D_OK;
+}
+
+s5d_status s5d_server_tick(s5d_server* s, int32_t* n_running, int32_t* n_queued) {
+  s5d::clear_error();
+  if (!s) return fail(S5D_EINVAL, "server is NULL");
+  s5d_status st = retire(s);
+  if (st != S5D_OK) return st;
+  // 1. admission, FIFO under the budget
+  hipEvent_t fin_ev = nullptr;
+  std::vector<Request*> fin;
+  while (!s->queue.empty()) {
+    Request* r = s->queue.front();
+    if (s->cfg.max_running > 0 && static_cast<int64_t>(s->running.size()) >= s->cfg.max_running) break;
+    if (s->used + r->bytes2 > s->cfg.hbm_budget_bytes) break;
+    st = admit(s, r);
+    if (st != S5D_OK) return st;
+    s->used += r->bytes2;
+    s->peak = std::max(s->peak, s->used);
+    s->queue.pop_front();
+    if (r->rounds.empty())
+      fin.push_back(r);  // zero steps: the result is the initial grid
+    else
+      s->running.push_back(r);
+  }
+  // 2. one round of every running request
+  if (!s->running.empty()) {
+    std::vector<s5d::RoundItem> items;
+    items.reserve(s->running.size());
+    for (Request* r : s->running) {
+      const size_t k = r->next++;
+      items.push_back(s5d::RoundItem{&r->plan, r->rounds[k], r->buf[k % 2], r->buf[(k + 1) % 2]});
+    }
+    std::vector<unsigned char> blob;
+    std::vector<s5d::GroupLaunch> launches;
+    st = s5d::build_step(items, blob, launches);
+    if (st != S5D_OK) return st;
+    Slot& sl = s->slots[s->ticks % kSlots];
+    if (sl.pending) {
+      const hipError_t e = hipEventSynchronize(sl.ev);  // paces the host: at most kSlots ticks in flight
+      if (e != hipSuccess) return device_fail(e, "hipEventSynchronize");
+      sl.pending = false;
+    }
+    st = grow_slot(sl, blob.size());
+    if (st != S5D_OK) return st;
+    std::memcpy(sl.host, blob.data(), blob.size());
+    hipError_t e = hipMemcpyAsync(sl.dev, sl.host, blob.size(), hipMemcpyHostToDevice, s->stream);
+    if (e != hipSuccess) return device_fail(e, "tick table upload");
+    e = s5d::enqueue_step(launches, sl.dev, s->stream);
+    if (e != hipSuccess) return device_fail(e, "tick launch");
+    e = hipEventRecord(sl.ev, s->stream);
+    if (e != hipSuccess) return device_fail(e, "hipEventRecord");
+    sl.pending = true;
+    ++s->ticks;
+    s->launches += static_cast<int64_t>(launches.size());
+    std::vector<Request*> still;
+    for (Request* r : s->running) {
+      if (r->next == r->rounds.size())
+        fin.push_back(r);
+      else
+        still.push_back(r);
+    }
+    s->running.swap(still);
+  }
+  if (!fin.empty()) {
+    st = take_event(s, &fin_ev);
+    if (st != S5D_OK) return st;
+    const hipError_t e = hipEventRecord(fin_ev, s->stream);
+    if (e != hipSuccess) return device_fail(e, "hipEventRecord");
+    for (Request* r : fin)
+      if (!r->keep) release_buffers(s, r);
+    s->finishing.push_back(Finishing{fin_ev, fin});
+  }
+  if (n_running) *n_running = static_cast<int32_t>(s->running.size());
+  if (n_queued) *n_queued = static_cast<int32_t>(s->queue.size());
+  return S5D_OK;
+}
+
+s5d_status s5d_server_sync(s5d_server* s) {
+  s5d::clear_error();
+  if (!s) return fail(S5D_EINVAL, "server is NULL");
+  const hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return device_fail(e, "hipStreamSynchronize");
+  return retire(s);
+}
+
+s5d_status s5d_server_request(const s5d_server* s, int64_t id, s5d_request_info* info) {
+  s5d::clear_error();
+  if (!s || !info) return fail(S5D_EINVAL, "server and info must not be NULL");
+  if (info->struct_size < sizeof(s5d_request_info)) return fail(S5D_EINVAL, "info->struct_size too small");
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return fail(S5D_EINVAL, "unknown request id");
+  const Request* r = it->second.get();
+  info->state = r->state;
+  info->result_index = static_cast<int32_t>(r->plan.d.steps % 2);
+  info->updates = r->updates;
+  info->t_arrival = r->t_arrival;
+  info->t_admit = r->t_admit;
+  info->t_done = r->t_done;
+  info->rounds_done = static_cast<int64_t>(r->next);
+  return S5D_OK;
+}
+
+s5d_status s5d_server_fetch(s5d_server* s, int64_t id, void* dst) {
+  s5d::clear_error();
+  if (!s || !dst) return fail(S5D_EINVAL, "server and dst must not be NULL");
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return fail(S5D_EINVAL, "unknown request id");
+  Request* r = it->second.get();
+  if (r->state != S5D_REQ_DONE || !r->keep || !r->buf[0])
+    return fail(S5D_EINVAL, "request is not finished or its result was not kept");
+  const int64_t T = r->plan.d.steps;
+  hipError_t e =
+      hipMemcpyAsync(dst, r->buf[T % 2], static_cast<size_t>(r->plan.bytes), hipMemcpyDefault, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return device_fail(e, "result copy");
+  release_buffers(s, r);
+  r->state = S5D_REQ_RELEASED;
+  return S5D_OK;
+}
+
+s5d_status s5d_server_get_stats(const s5d_server* s, s5d_server_stats* out) {
+  s5d::clear_error();
+  if (!s || !out) return fail(S5D_EINVAL, "server and out must not be NULL");
+  if (out->struct_size < sizeof(s5d_server_stats)) return fail(S5D_EINVAL, "out->struct_size too small");
+  out->submitted = static_cast<int64_t>(s->reqs.size());
+  out->queued = static_cast<int64_t>(s->queue.size());
+  out->running = static_cast<int64_t>(s->running.size());
+  out->done = s->done;
+  out->bytes_in_use = s->used;
+  out->bytes_peak = s->peak;
+  out->ticks = s->ticks;
+  out->launches = s->launches;
+  out->updates_done = s->updates_done;
+  out->latency_p50 = percentile(s->latencies, 0.50);
+  out->latency_p99 = percentile(s->latencies, 0.99);
+  out->makespan = (s->done > 0 && s->first_arrival >= 0) ? s->last_done - s->first_arrival : 0.0;
+  return S5D_OK;
+}
+
+}  // extern "C"

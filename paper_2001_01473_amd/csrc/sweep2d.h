@@ -241,15 +241,14 @@ __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPac
   for (int it = 1; it < niter; ++it) iteration(s0 + it * NS);
 }
 
+// Workgroup lb of one grid's launch: kWavesPerBlock waves, one tile each.
 template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
-__global__ __launch_bounds__(64 * kWavesPerBlock) void sweep2d_kernel(Sweep2DArgs a,
-                                                                    CoefPack<T, npts(2, R, BOX)> cf) {
+__device__ __forceinline__ void sweep2d_block(const Sweep2DArgs& a, const CoefPack<T, npts(2, R, BOX)>& cf, int lb,
+                                              EdgeStash<T, R, BT, CPL>* stash) {
   constexpr int W = 64 * CPL;
   constexpr int C = W - 2 * BT * R;
   static_assert(R <= CPL, "the lane exchange reaches one neighbouring lane only");
   static_assert(C >= 1, "tile narrower than its overlap");
-  __shared__ EdgeStash<T, R, BT, CPL> stash[kWavesPerBlock];
-  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wid = lb * kWavesPerBlock + wib;
   if (wid >= a.nwaves) return;
@@ -270,10 +269,37 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void sweep2d_kernel(Sweep2DArg
 }
 
 template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
-hipError_t launch_sweep2d(const Round2D& rd) {
+__global__ __launch_bounds__(64 * kWavesPerBlock) void sweep2d_kernel(Sweep2DArgs a,
+                                                                    CoefPack<T, npts(2, R, BOX)> cf) {
+  __shared__ EdgeStash<T, R, BT, CPL> stash[kWavesPerBlock];
+  sweep2d_block<T, ACC, R, BOX, BT, CPL, NR>(a, cf, xcd_logical_block(blockIdx.x, gridDim.x), stash);
+}
+
+// One grid of a batched launch: its geometry and coefficients.
+template <typename T, int NP>
+struct alignas(16) Item2D {
+  Sweep2DArgs a;
+  CoefPack<T, NP> cf;
+};
+
+// Batched launch: workgroup b runs workgroup map[b].block of grid map[b].item.
+// Item and map are read once per wave with scalar loads (uniform addresses)
+// and copied into registers before the sweep starts.
+template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
+__global__ __launch_bounds__(64 * kWavesPerBlock) void sweep2d_batch_kernel(
+    const Item2D<T, npts(2, R, BOX)>* __restrict__ items, const BlockMap* __restrict__ map) {
+  __shared__ EdgeStash<T, R, BT, CPL> stash[kWavesPerBlock];
+  const BlockMap m = map[xcd_logical_block(blockIdx.x, gridDim.x)];
+  const Item2D<T, npts(2, R, BOX)>& it = items[__builtin_amdgcn_readfirstlane(m.item)];
+  const Sweep2DArgs a = it.a;
+  const CoefPack<T, npts(2, R, BOX)> cf = it.cf;
+  sweep2d_block<T, ACC, R, BOX, BT, CPL, NR>(a, cf, __builtin_amdgcn_readfirstlane(m.block), stash);
+}
+
+template <typename T, int R, bool BOX, int BT, int CPL>
+Sweep2DArgs make_args2d(const Round2D& rd, CoefPack<T, npts(2, R, BOX)>& cf) {
   constexpr int NP = npts(2, R, BOX);
   constexpr int C = 64 * CPL - 2 * BT * R;
-  CoefPack<T, NP> cf;
   for (int k = 0; k < NP; ++k) cf.c[k] = static_cast<T>(rd.coeffs[k]);
   Sweep2DArgs a;
   a.src = rd.src;
@@ -285,9 +311,32 @@ hipError_t launch_sweep2d(const Round2D& rd) {
   const int nchunks = (rd.I0 + rd.chunk - 1) / rd.chunk;
   a.nwaves = a.ntiles * nchunks;
   a.pad = 0;
+  return a;
+}
+
+template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
+hipError_t launch_sweep2d(const Round2D& rd) {
+  CoefPack<T, npts(2, R, BOX)> cf;
+  const Sweep2DArgs a = make_args2d<T, R, BOX, BT, CPL>(rd, cf);
   const int nblk = (a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
   hipLaunchKernelGGL((sweep2d_kernel<T, ACC, R, BOX, BT, CPL, NR>), dim3(nblk), dim3(64 * kWavesPerBlock), 0,
                      rd.stream, a, cf);
+  return hipGetLastError();
+}
+
+template <typename T, int R, bool BOX, int BT, int CPL>
+int fill_item2d(void* item, const Round2D& rd) {
+  Item2D<T, npts(2, R, BOX)> it;
+  it.a = make_args2d<T, R, BOX, BT, CPL>(rd, it.cf);
+  __builtin_memcpy(item, &it, sizeof(it));
+  return (it.a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
+}
+
+template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
+hipError_t launch_batch2d(const void* items, const BlockMap* map, int nblocks, hipStream_t stream) {
+  hipLaunchKernelGGL((sweep2d_batch_kernel<T, ACC, R, BOX, BT, CPL, NR>), dim3(nblocks),
+                     dim3(64 * kWavesPerBlock), 0, stream,
+                     static_cast<const Item2D<T, npts(2, R, BOX)>*>(items), map);
   return hipGetLastError();
 }
 
@@ -302,8 +351,14 @@ int occupancy_sweep2d() {
 
 template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
 Kernel2D make_kernel2d() {
-  return Kernel2D{&launch_sweep2d<T, ACC, R, BOX, BT, CPL, NR>, &occupancy_sweep2d<T, ACC, R, BOX, BT, CPL, NR>, CPL, BT,
-                  64 * CPL};
+  return Kernel2D{&launch_sweep2d<T, ACC, R, BOX, BT, CPL, NR>,
+                  &occupancy_sweep2d<T, ACC, R, BOX, BT, CPL, NR>,
+                  CPL,
+                  BT,
+                  64 * CPL,
+                  &fill_item2d<T, R, BOX, BT, CPL>,
+                  &launch_batch2d<T, ACC, R, BOX, BT, CPL, NR>,
+                  static_cast<int>(sizeof(Item2D<T, npts(2, R, BOX)>))};
 }
 
 }  // namespace s5d

@@ -251,14 +251,14 @@ __device__ __forceinline__ void sweep3d_body(const Sweep3DArgs& a, const CoefPac
   for (int it = 1; it < niter; ++it) iteration(s0 + it * NS);
 }
 
+// Workgroup lb of one grid's launch: one (tile, stream block) pair.
 template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
-__global__ __launch_bounds__(64 * NW) void sweep3d_kernel(Sweep3DArgs a, CoefPack<T, npts(3, R, BOX)> cf) {
+__device__ __forceinline__ void sweep3d_block(const Sweep3DArgs& a, const CoefPack<T, npts(3, R, BOX)>& cf, int lb,
+                                              T (&xbuf)[2][NW][2 * R][64 * CPL]) {
   constexpr int B1 = NW * M, B2 = 64 * CPL;
   constexpr int C1 = B1 - 2 * BT * R, C2 = B2 - 2 * BT * R;
   static_assert(R <= CPL, "the lane exchange reaches one neighbouring lane only");
   static_assert(C1 >= 1 && C2 >= 1, "tile narrower than its overlap");
-  __shared__ T xbuf[2][NW][2 * R][64 * CPL];
-  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const int t2 = lb % a.nt2;
   const int t1 = (lb / a.nt2) % a.nt1;
   const int chunk = lb / (a.nt2 * a.nt1);
@@ -278,12 +278,37 @@ __global__ __launch_bounds__(64 * NW) void sweep3d_kernel(Sweep3DArgs a, CoefPac
 }
 
 template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
-hipError_t launch_sweep3d(const Round3D& rd) {
+__global__ __launch_bounds__(64 * NW) void sweep3d_kernel(Sweep3DArgs a, CoefPack<T, npts(3, R, BOX)> cf) {
+  __shared__ T xbuf[2][NW][2 * R][64 * CPL];
+  sweep3d_block<T, ACC, R, BOX, BT, CPL, M, NW, NR>(a, cf, xcd_logical_block(blockIdx.x, gridDim.x), xbuf);
+}
+
+// One grid of a batched launch: its geometry and coefficients.
+template <typename T, int NP>
+struct alignas(16) Item3D {
+  Sweep3DArgs a;
+  CoefPack<T, NP> cf;
+};
+
+// Batched launch: workgroup b runs workgroup map[b].block of grid map[b].item.
+template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
+__global__ __launch_bounds__(64 * NW) void sweep3d_batch_kernel(const Item3D<T, npts(3, R, BOX)>* __restrict__ items,
+                                                              const BlockMap* __restrict__ map) {
+  __shared__ T xbuf[2][NW][2 * R][64 * CPL];
+  const BlockMap m = map[xcd_logical_block(blockIdx.x, gridDim.x)];
+  const Item3D<T, npts(3, R, BOX)>& it = items[__builtin_amdgcn_readfirstlane(m.item)];
+  const Sweep3DArgs a = it.a;
+  const CoefPack<T, npts(3, R, BOX)> cf = it.cf;
+  sweep3d_block<T, ACC, R, BOX, BT, CPL, M, NW, NR>(a, cf, __builtin_amdgcn_readfirstlane(m.block), xbuf);
+}
+
+// Geometry of one grid's launch; returns its workgroup count (0 if it does
+// not fit a 32-bit grid).
+template <typename T, int R, bool BOX, int BT, int CPL, int M, int NW>
+int64_t make_args3d(const Round3D& rd, Sweep3DArgs& a, CoefPack<T, npts(3, R, BOX)>& cf) {
   constexpr int NP = npts(3, R, BOX);
   constexpr int C1 = NW * M - 2 * BT * R, C2 = 64 * CPL - 2 * BT * R;
-  CoefPack<T, NP> cf;
   for (int k = 0; k < NP; ++k) cf.c[k] = static_cast<T>(rd.coeffs[k]);
-  Sweep3DArgs a;
   a.src = rd.src;
   a.dst = rd.dst;
   a.I0 = rd.I0;
@@ -294,9 +319,32 @@ hipError_t launch_sweep3d(const Round3D& rd) {
   a.nt2 = (rd.I2 + C2 - 1) / C2;
   const int nchunks = (rd.I0 + rd.chunk - 1) / rd.chunk;
   const int64_t nblk = static_cast<int64_t>(a.nt1) * a.nt2 * nchunks;
-  if (nblk > INT32_MAX) return hipErrorInvalidConfiguration;
+  return nblk > INT32_MAX ? 0 : nblk;
+}
+
+template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
+hipError_t launch_sweep3d(const Round3D& rd) {
+  Sweep3DArgs a;
+  CoefPack<T, npts(3, R, BOX)> cf;
+  const int64_t nblk = make_args3d<T, R, BOX, BT, CPL, M, NW>(rd, a, cf);
+  if (nblk == 0) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((sweep3d_kernel<T, ACC, R, BOX, BT, CPL, M, NW, NR>), dim3(static_cast<unsigned>(nblk)),
                      dim3(64 * NW), 0, rd.stream, a, cf);
+  return hipGetLastError();
+}
+
+template <typename T, int R, bool BOX, int BT, int CPL, int M, int NW>
+int fill_item3d(void* item, const Round3D& rd) {
+  Item3D<T, npts(3, R, BOX)> it;
+  const int64_t nblk = make_args3d<T, R, BOX, BT, CPL, M, NW>(rd, it.a, it.cf);
+  __builtin_memcpy(item, &it, sizeof(it));
+  return static_cast<int>(nblk);
+}
+
+template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
+hipError_t launch_batch3d(const void* items, const BlockMap* map, int nblocks, hipStream_t stream) {
+  hipLaunchKernelGGL((sweep3d_batch_kernel<T, ACC, R, BOX, BT, CPL, M, NW, NR>), dim3(nblocks), dim3(64 * NW), 0,
+                     stream, static_cast<const Item3D<T, npts(3, R, BOX)>*>(items), map);
   return hipGetLastError();
 }
 
@@ -311,8 +359,15 @@ int occupancy_sweep3d() {
 
 template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
 Kernel3D make_kernel3d() {
-  return Kernel3D{&launch_sweep3d<T, ACC, R, BOX, BT, CPL, M, NW, NR>, &occupancy_sweep3d<T, ACC, R, BOX, BT, CPL, M, NW, NR>,
-                  CPL, M, NW, BT};
+  return Kernel3D{&launch_sweep3d<T, ACC, R, BOX, BT, CPL, M, NW, NR>,
+                  &occupancy_sweep3d<T, ACC, R, BOX, BT, CPL, M, NW, NR>,
+                  CPL,
+                  M,
+                  NW,
+                  BT,
+                  &fill_item3d<T, R, BOX, BT, CPL, M, NW>,
+                  &launch_batch3d<T, ACC, R, BOX, BT, CPL, M, NW, NR>,
+                  static_cast<int>(sizeof(Item3D<T, npts(3, R, BOX)>))};
 }
 
 }  // namespace s5d

@@ -1,0 +1,149 @@
+"""GPU tests of batched execution (s5d_batch_*).
+
+Bars: every grid of a batch is bit-identical to the same grid run alone with
+s5d_run (same plan), eager and graph-replayed alike; grids of the float64
+kinds are also within 1e-12 of the oracle, float32 grids within the a-priori
+bound.  The many-grid workload (64 2D star grids, sides U{256..4096}, radius
+1 or 2, float32, 200 steps) is checked in full against single runs and, for
+its eight smallest grids, against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2001_01473_amd as s5d
+import pins
+import stencil_inputs as si
+from gpu_util import rel_errors, say, torch
+
+pytestmark = pytest.mark.gpu
+
+DT = {"f32": np.float32, "f64": np.float64}
+
+
+def _plan(spec, dtype, accum="plain", **tuning):
+    case = si.make_case(spec["seed"], spec["ndim"], spec["radius"], spec["box"],
+                        spec["interior"], spec["steps"])
+    c_in, g_in = case.as_dtype(dtype)
+    plan = s5d.Plan(ndim=spec["ndim"], radius=spec["radius"], box=spec["box"], dtype=dtype,
+                    interior=spec["interior"], steps=spec["steps"], coeffs=case.coeffs,
+                    accum=accum, **tuning)
+    return plan, g_in, c_in
+
+
+def _alone(plan, g_in):
+    t = torch()
+    x = t.from_numpy(g_in).to("cuda:0")
+    y = t.empty_like(x)
+    idx = plan.run(x, y)
+    t.cuda.synchronize()
+    return (x if idx == 0 else y).cpu().numpy()
+
+
+def _run_batch(plans, grids, graph, repeats=1):
+    t = torch()
+    b0 = [t.from_numpy(g).to("cuda:0") for g in grids]
+    b1 = [t.empty_like(x) for x in b0]
+    batch = s5d.Batch(plans, b0, b1, graph=graph)
+    outs = []
+    for rep in range(repeats):
+        if rep:
+            for x, g in zip(b0, grids):  # eager work between replays
+                x.copy_(t.from_numpy(g))
+            t.cuda.synchronize()
+        idx = batch.run()
+        t.cuda.synchronize()
+        outs.append([(b0[i] if idx[i] == 0 else b1[i]).cpu().numpy() for i in range(len(plans))])
+    info = batch.query()
+    batch.close()
+    return outs, info
+
+
+def _mixed_specs():
+    specs = []
+    shapes = [(2, 1, False, (300, 517)), (2, 2, False, (77, 1030)), (2, 1, True, (129, 65)),
+              (2, 2, True, (260, 300)), (3, 1, False, (40, 37, 150)), (3, 1, True, (21, 19, 70)),
+              (2, 1, False, (5, 3)), (2, 3, False, (200, 211))]
+    for j, (nd, r, box, interior) in enumerate(shapes):
+        for T in (0, 1, 6, 13):
+            specs.append(dict(ndim=nd, radius=r, box=box, interior=interior, steps=T,
+                              seed=si.item_seed(77, 10 * j + T)))
+    return specs
+
+
+@pytest.mark.parametrize("graph", [False, True])
+@pytest.mark.parametrize("kind", ["f32", "f64", "f32c"])
+def test_mixed_batch_equals_alone(kind, graph):
+    dtype = np.float32 if kind != "f64" else np.float64
+    accum = "compensated" if kind == "f32c" else "plain"
+    specs = _mixed_specs()
+    made = [_plan(s, dtype, accum) for s in specs]
+    plans = [m[0] for m in made]
+    grids = [m[1] for m in made]
+    say("batch mixed", kind, "graph" if graph else "eager", len(specs), "grids")
+    outs, info = _run_batch(plans, grids, graph, repeats=3 if graph else 1)
+    lo = max(-(-p.steps // p.query()["bt"]) for p in plans)
+    assert lo <= info["round_steps"] <= lo + 2
+    for i, (p, g) in enumerate(zip(plans, grids)):
+        alone = _alone(p, g)
+        for rep, out in enumerate(outs):
+            np.testing.assert_array_equal(out[i], alone, err_msg="grid %d replay %d" % (i, rep))
+    for i, ((p, g, c), s) in enumerate(zip(made, specs)):
+        ref_kw = dict(radius=s["radius"], box=s["box"], steps=s["steps"])
+        if kind == "f64":
+            ref = oracle.sweep(g, coeffs=c, **ref_kw)
+            assert max(rel_errors(outs[0][i], ref)) <= 1e-12
+        elif kind == "f32c":
+            ref = oracle.sweep(g, coeffs=c, accum="compensated", **ref_kw)
+            np.testing.assert_array_equal(outs[0][i], ref)
+
+
+def test_batch_launch_count_and_empty():
+    specs = [dict(ndim=2, radius=1, box=False, interior=(600, 700), steps=40,
+                  seed=si.item_seed(5, j)) for j in range(16)]
+    made = [_plan(s, np.float32) for s in specs]
+    t = torch()
+    b0 = [t.from_numpy(m[1]).to("cuda:0") for m in made]
+    b1 = [t.empty_like(x) for x in b0]
+    batch = s5d.Batch([m[0] for m in made], b0, b1)
+    q = batch.query()
+    # one boundary copy per grid plus one launch per round index (one variant)
+    assert q["launches"] == 16 + q["round_steps"]
+    batch.close()
+    empty = s5d.Batch([], [], [])
+    assert empty.run() == [] and empty.query() == {"launches": 0, "round_steps": 0}
+    empty.close()
+
+
+def test_batch_rejects_shared_buffers():
+    spec = dict(ndim=2, radius=1, box=False, interior=(64, 64), steps=3, seed=1)
+    p, g, _ = _plan(spec, np.float64)
+    t = torch()
+    a, b = t.from_numpy(g).to("cuda:0"), t.empty(g.shape, dtype=t.float64, device="cuda:0")
+    with pytest.raises(s5d.Stencil5DError) as err:
+        s5d.Batch([p, p], [a, a], [b, t.empty_like(b)])
+    assert err.value.status == 1
+
+
+def test_many_grid_workload_bitwise_and_oracle():
+    """64 2D star grids, sides U{256..4096}, radius 1 or 2, float32, T = 200,
+    default tuning, one graph: all 64 bit-identical to single runs, the eight
+    smallest within the float32 bound of the float64 oracle."""
+    specs = si.batch_mix(si.workload_seed(3))
+    made = [_plan(s, np.float32) for s in specs]
+    plans, grids = [m[0] for m in made], [m[1] for m in made]
+    say("batch 64 grids, graph")
+    outs, info = _run_batch(plans, grids, graph=True, repeats=2)
+    say("batch launches", info)
+    for i in range(len(plans)):
+        alone = _alone(plans[i], grids[i])
+        np.testing.assert_array_equal(outs[0][i], alone, err_msg="grid %d" % i)
+        np.testing.assert_array_equal(outs[1][i], alone, err_msg="grid %d replay" % i)
+    order = sorted(range(len(specs)), key=lambda i: np.prod(specs[i]["interior"]))[:8]
+    for i in order:
+        s, (p, g, c) = specs[i], made[i]
+        ref = oracle.sweep(g.astype(np.float64), radius=s["radius"], box=False,
+                           coeffs=c.astype(np.float64), steps=s["steps"])
+        n = len(c)
+        bound = s["steps"] * (pins.gamma(n, pins.U32) + pins.U32) * float(g.max()) * 1.01
+        assert float(np.max(np.abs(outs[0][i].astype(np.float64) - ref))) <= bound, i
