@@ -94,7 +94,15 @@ typedef struct s5d_tuning {
     int32_t cells_per_lane; /* consecutive cells of the last axis owned by one lane */
     int32_t rows_per_wave;  /* 3D: consecutive axis-1 rows held by one wave */
     int32_t waves_per_eu;   /* reserved, 0 */
+    int32_t kernel;         /* S5D_KERNEL_*: which kernel family runs the sweep */
 } s5d_tuning;
+
+/* Kernel families (s5d_tuning.kernel). */
+#define S5D_KERNEL_AUTO 0    /* temporally blocked where compiled, else direct */
+#define S5D_KERNEL_BLOCKED 1 /* b_T fused steps per launch (AN5D "Execution Model") */
+#define S5D_KERNEL_DIRECT 2  /* one step per launch from an LDS-staged tile; covers every
+                                radius 1..4 and shape, for stencils whose blocked state
+                                does not fit a lane (the plan's bt is 1) */
 
 typedef struct s5d_plan s5d_plan; /* opaque; immutable once created */
 
@@ -299,7 +307,9 @@ s5d_status s5d_server_submit(s5d_server *server, const s5d_plan *plan, const voi
                              double arrival, int32_t keep_result, int64_t *id);
 
 /* One tick (see above).  n_running / n_queued (may be NULL) receive the
- * counts after it. */
+ * counts after it.  n_running = 0 with n_queued > 0 means the next queued
+ * request does not fit beside the kept results: it waits until they are
+ * fetched. */
 s5d_status s5d_server_tick(s5d_server *server, int32_t *n_running, int32_t *n_queued);
 
 /* Wait for all enqueued work and record the completions. */

@@ -22,7 +22,7 @@ __all__ = ["Plan", "Batch", "Server", "solve", "error_norms", "autotune", "tune_
            "STAR", "BOX", "F32", "F64", "ACC_PLAIN", "ACC_COMPENSATED"]
 
 _TUNING_KEYS = ("bt", "tile0", "tile1", "stream_chunk", "cells_per_lane", "rows_per_wave",
-                "waves_per_eu")
+                "waves_per_eu", "kernel")
 
 
 def _dtype_code(dtype):

@@ -49,7 +49,8 @@ class S5DTuning(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("bt", ctypes.c_int32),
                 ("tile0", ctypes.c_int32), ("tile1", ctypes.c_int32),
                 ("stream_chunk", ctypes.c_int32), ("cells_per_lane", ctypes.c_int32),
-                ("rows_per_wave", ctypes.c_int32), ("waves_per_eu", ctypes.c_int32)]
+                ("rows_per_wave", ctypes.c_int32), ("waves_per_eu", ctypes.c_int32),
+                ("kernel", ctypes.c_int32)]
 
 
 class S5DServerConfig(ctypes.Structure):
@@ -219,11 +220,15 @@ def make_desc(ndim, radius, box, dtype, accum, interior, steps, coeffs):
     return d, c  # keep c alive while d is used
 
 
+KERNELS = {"auto": 0, "blocked": 1, "direct": 2}
+
+
 def make_tuning(bt=0, tile0=0, tile1=0, stream_chunk=0, cells_per_lane=0, rows_per_wave=0,
-                waves_per_eu=0):
+                waves_per_eu=0, kernel=0):
     t = S5DTuning()
     t.struct_size = ctypes.sizeof(S5DTuning)
     t.bt, t.tile0, t.tile1 = int(bt), int(tile0), int(tile1)
     t.stream_chunk, t.cells_per_lane = int(stream_chunk), int(cells_per_lane)
     t.rows_per_wave, t.waves_per_eu = int(rows_per_wave), int(waves_per_eu)
+    t.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     return t

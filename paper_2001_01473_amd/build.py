@@ -41,9 +41,9 @@ DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                 "-I" + CSRC, "-I" + INCLUDE]
 
-HOST_SOURCES = ["abi.cpp", "batch.cpp", "server.cpp", "tune.cpp", "halo.hip", "norms.hip"]
+HOST_SOURCES = ["abi.cpp", "batch.cpp", "server.cpp", "tune.cpp", "halo.hip", "norms.hip", "direct.hip"]
 HEADERS = ["s5d_internal.h", "kcommon.h", "sweep2d.h", "sweep3d.h"]
-HOST_HEADERS = ["host.h", "batch.h", "norms.h"]  # included by host sources only
+HOST_HEADERS = ["host.h", "batch.h", "norms.h", "direct.h"]  # not included by the variant units
 
 # Kernel kinds: (name, C++ type, 32-bit words per element, accumulation
 # policy).  Kind 2 is float32 with compensated (Dot2) accumulation.

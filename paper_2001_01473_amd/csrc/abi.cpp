@@ -50,9 +50,12 @@ using s5d::fail;
 namespace {
 
 // Largest radius with kernels, per dimensionality and shape.
+// (radius 1..4 for every shape: the direct kernels cover what no blocked
+// variant does)
 int max_radius(int ndim, int shape) {
-  if (ndim == 2) return shape == S5D_STAR ? 4 : 2;
-  return 2;
+  (void)ndim;
+  (void)shape;
+  return 4;
 }
 
 const Entry3D* find3d(int kind, int box, int r, int cpl, int m, int nw, int bt) {
@@ -71,6 +74,22 @@ int default_bt3(int kind, int box, int r) {
   if (kind == KIND_F32_COMP) return 1;
   if (r == 1) return box ? 3 : 4;
   return box ? 1 : 2;
+}
+
+// Is any blocked variant compiled for this stencil?
+bool has_blocked(int kind, int ndim, int box, int r) {
+  if (ndim == 2) {
+    for (int i = 0; i < s5d::kRegistry2DSize; ++i) {
+      const Entry2D& e = s5d::kRegistry2D[i];
+      if (e.dtype == kind && e.box == box && e.r == r) return true;
+    }
+    return false;
+  }
+  for (int i = 0; i < s5d::kRegistry3DSize; ++i) {
+    const Entry3D& e = s5d::kRegistry3D[i];
+    if (e.dtype == kind && e.box == box && e.r == r) return true;
+  }
+  return false;
 }
 
 const Entry2D* find2d(int kind, int box, int r, int cpl, int bt) {
@@ -199,6 +218,46 @@ RoundSchedule schedule_rounds(int64_t T, int bt) {
 
 namespace {
 
+// Direct kernels: one step per launch; the device coefficient table is made
+// here (the only device allocation of a plan).
+s5d_status plan_direct(s5d_plan* p, const s5d_tuning& req, int box, int r) {
+  if (req.bt > 1 || req.cells_per_lane > 0 || req.rows_per_wave > 0 || req.tile0 > 0 || req.tile1 > 0 ||
+      req.stream_chunk > 0)
+    return fail(S5D_EINVAL, "direct kernels take no blocking parameters");
+  if (p->d.ndim == 2) {
+    p->by_bt[1] = s5d::direct_kernel2d(p->kind, r, box != 0);
+    if (!p->by_bt[1].launch) return fail(S5D_EUNSUPPORTED, "no direct 2D kernel for this stencil");
+    p->tun.tile0 = p->by_bt[1].tile;
+  } else {
+    p->by_bt3[1] = s5d::direct_kernel3d(p->kind, r, box != 0);
+    if (!p->by_bt3[1].launch) return fail(S5D_EUNSUPPORTED, "no direct 3D kernel for this stencil");
+    p->tun.tile0 = p->by_bt3[1].m;
+  }
+  p->direct = true;
+  p->tun.bt = 1;
+  p->tun.kernel = S5D_KERNEL_DIRECT;
+  const size_t n = p->coeffs.size();
+  std::vector<unsigned char> host(n * static_cast<size_t>(p->elem));
+  for (size_t k = 0; k < n; ++k) {
+    if (p->elem == 4) {
+      const float v = static_cast<float>(p->coeffs[k]);
+      std::memcpy(host.data() + 4 * k, &v, 4);
+    } else {
+      std::memcpy(host.data() + 8 * k, &p->coeffs[k], 8);
+    }
+  }
+  void* dev = nullptr;
+  hipError_t e = hipMalloc(&dev, host.size());
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return device_fail(e, "hipMalloc of the coefficient table");
+  }
+  p->dcoef = std::shared_ptr<void>(dev, [](void* q) { (void)hipFree(q); });
+  e = hipMemcpy(dev, host.data(), host.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return device_fail(e, "upload of the coefficient table");
+  return S5D_OK;
+}
+
 s5d_status plan_2d(s5d_plan* p, const s5d_tuning& req, int box, int r) {
   const s5d_desc& d = p->d;
   int cpl = req.cells_per_lane;
@@ -323,6 +382,7 @@ std::vector<int> plan_rounds(const s5d_plan* p) {
 namespace {
 Round2D round2d(const s5d_plan* p, const void* src, void* dst, hipStream_t stream) {
   Round2D rd;
+  rd.dcoef = p->dcoef.get();
   rd.src = src;
   rd.dst = dst;
   rd.I0 = static_cast<int32_t>(p->d.interior[0]);
@@ -334,6 +394,7 @@ Round2D round2d(const s5d_plan* p, const void* src, void* dst, hipStream_t strea
 }
 Round3D round3d(const s5d_plan* p, const void* src, void* dst, hipStream_t stream) {
   Round3D rd;
+  rd.dcoef = p->dcoef.get();
   rd.src = src;
   rd.dst = dst;
   rd.I0 = static_cast<int32_t>(p->d.interior[0]);
@@ -441,6 +502,8 @@ s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_p
     if (req.bt < 0 || req.tile0 < 0 || req.tile1 < 0 || req.stream_chunk < 0 || req.cells_per_lane < 0 ||
         req.waves_per_eu < 0)
       return fail(S5D_EINVAL, "tuning fields must be >= 0");
+    if (req.kernel != S5D_KERNEL_AUTO && req.kernel != S5D_KERNEL_BLOCKED && req.kernel != S5D_KERNEL_DIRECT)
+      return fail(S5D_EINVAL, "kernel must be S5D_KERNEL_AUTO, _BLOCKED or _DIRECT");
     if (req.bt > 15) return fail(S5D_EINVAL, "bt must be <= 15");
   }
 
@@ -468,6 +531,8 @@ s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_p
       p->by_bt[b] = Kernel2D{};
       p->by_bt3[b] = Kernel3D{};
     }
+    p->direct = false;
+    p->dcoef.reset();
     std::memset(&p->tun, 0, sizeof(p->tun));
     p->tun.struct_size = sizeof(s5d_tuning);
   };
@@ -483,7 +548,23 @@ s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_p
       reset();
     }
   }
-  if (st != S5D_OK) st = d.ndim == 2 ? plan_2d(p, req, box, r) : plan_3d(p, req, box, r);
+  if (st != S5D_OK) {
+    if (req.kernel == S5D_KERNEL_DIRECT) {
+      st = plan_direct(p, req, box, r);
+    } else {
+      st = d.ndim == 2 ? plan_2d(p, req, box, r) : plan_3d(p, req, box, r);
+      // no blocked variant for this stencil: the direct kernels, unless the
+      // caller asked for blocking or gave blocking parameters
+      if (st == S5D_EUNSUPPORTED && req.kernel == S5D_KERNEL_AUTO && req.bt <= 1 && req.cells_per_lane == 0 &&
+          req.rows_per_wave == 0 && req.tile0 == 0 && req.tile1 == 0 && req.stream_chunk == 0 &&
+          !has_blocked(p->kind, d.ndim, box, r)) {
+        g_last_error.clear();
+        reset();
+        st = plan_direct(p, req, box, r);
+      }
+    }
+  }
+  if (st == S5D_OK) p->tun.kernel = p->direct ? S5D_KERNEL_DIRECT : S5D_KERNEL_BLOCKED;
   if (st != S5D_OK) {
     delete p;
     return st;

@@ -1,0 +1,79 @@
+// Instantiations of the direct kernels: every kernel kind, radius 1..4 and
+// shape, in 2D and 3D.
+#include "direct.h"
+
+namespace s5d {
+namespace {
+
+template <typename T, int ACC, int R, bool BOX>
+Kernel2D make2d() {
+  return Kernel2D{&launch_direct2d<T, ACC, R, BOX>,
+                  &occupancy_direct<T, ACC, 2, R, BOX>,
+                  0,
+                  1,
+                  direct_dx<2, R>(),
+                  &fill_direct2d<R>,
+                  &launch_direct_batch<T, ACC, 2, R, BOX>,
+                  static_cast<int>(sizeof(DirectArgs))};
+}
+
+template <typename T, int ACC, int R, bool BOX>
+Kernel3D make3d() {
+  return Kernel3D{&launch_direct3d<T, ACC, R, BOX>,
+                  &occupancy_direct<T, ACC, 3, R, BOX>,
+                  0,
+                  kDirectY3,
+                  1,
+                  1,
+                  &fill_direct3d<R>,
+                  &launch_direct_batch<T, ACC, 3, R, BOX>,
+                  static_cast<int>(sizeof(DirectArgs))};
+}
+
+template <typename T, int ACC>
+Kernel2D pick2d(int r, bool box) {
+  switch (r * 2 + box) {
+    case 2: return make2d<T, ACC, 1, false>();
+    case 3: return make2d<T, ACC, 1, true>();
+    case 4: return make2d<T, ACC, 2, false>();
+    case 5: return make2d<T, ACC, 2, true>();
+    case 6: return make2d<T, ACC, 3, false>();
+    case 7: return make2d<T, ACC, 3, true>();
+    case 8: return make2d<T, ACC, 4, false>();
+    case 9: return make2d<T, ACC, 4, true>();
+    default: return Kernel2D{};
+  }
+}
+
+template <typename T, int ACC>
+Kernel3D pick3d(int r, bool box) {
+  switch (r * 2 + box) {
+    case 2: return make3d<T, ACC, 1, false>();
+    case 3: return make3d<T, ACC, 1, true>();
+    case 4: return make3d<T, ACC, 2, false>();
+    case 5: return make3d<T, ACC, 2, true>();
+    case 6: return make3d<T, ACC, 3, false>();
+    case 7: return make3d<T, ACC, 3, true>();
+    case 8: return make3d<T, ACC, 4, false>();
+    case 9: return make3d<T, ACC, 4, true>();
+    default: return Kernel3D{};
+  }
+}
+
+}  // namespace
+
+Kernel2D direct_kernel2d(int kind, int r, bool box) {
+  if (kind == KIND_F32) return pick2d<float, 0>(r, box);
+  if (kind == KIND_F64) return pick2d<double, 0>(r, box);
+  if (kind == KIND_F32_COMP) return pick2d<float, 1>(r, box);
+  return Kernel2D{};
+}
+
+Kernel3D direct_kernel3d(int kind, int r, bool box) {
+  if (kind == KIND_F32) return pick3d<float, 0>(r, box);
+  if (kind == KIND_F64) return pick3d<double, 0>(r, box);
+  if (kind == KIND_F32_COMP) return pick3d<float, 1>(r, box);
+  return Kernel3D{};
+}
+
+}  // namespace s5d

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -19,8 +20,12 @@ struct s5d_plan {
   int64_t bytes;
   int elem;
   int kind;                  // kernel kind: KIND_F32, KIND_F64 or KIND_F32_COMP
+  bool direct = false;       // direct kernels (one step per launch) instead of blocked ones
   s5d::Kernel2D by_bt[16];   // 2D: index bt -> kernel for a round of bt steps (same tile)
   s5d::Kernel3D by_bt3[16];  // 3D: likewise
+  // device copy of the coefficients in the working type (direct kernels);
+  // shared by copies of the plan, freed with the last of them
+  std::shared_ptr<void> dcoef;
 };
 
 namespace s5d {

@@ -25,7 +25,8 @@ struct Round2D {
   void* dst;
   int32_t I0, I1;   // interior extents (axis 0 streams)
   int32_t chunk;    // h_SN: output rows per stream block
-  const double* coeffs;
+  const double* coeffs;  // host, canonical order
+  const void* dcoef;     // device copy in the working type (direct kernels)
   hipStream_t stream;
 };
 
@@ -88,7 +89,8 @@ struct Round3D {
   void* dst;
   int32_t I0, I1, I2;  // interior extents (axis 0 streams)
   int32_t chunk;       // h_SN: output planes per stream block
-  const double* coeffs;
+  const double* coeffs;  // host, canonical order
+  const void* dcoef;     // device copy in the working type (direct kernels)
   hipStream_t stream;
 };
 
@@ -122,6 +124,12 @@ struct Entry3D {
 };
 extern const Entry3D kRegistry3D[];
 extern const int kRegistry3DSize;
+
+// Direct (one step per launch) kernels: the variant for a kernel kind,
+// dimensionality, radius (1..4) and shape (direct.hip).  As for the blocked
+// kernels, bt is 1 and tile fields describe the staged tile.
+Kernel2D direct_kernel2d(int kind, int r, bool box);
+Kernel3D direct_kernel3d(int kind, int r, bool box);
 
 // Copy the boundary cells (width r on every face) of a padded grid.
 hipError_t launch_halo_copy(const void* src, void* dst, int elem_bytes, int ndim,

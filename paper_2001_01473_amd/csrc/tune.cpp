@@ -105,6 +105,39 @@ RoundModel model_round2d(const s5d_plan* p, int bt) {
   return m;
 }
 
+// Direct kernels: one step per launch; HBM moves each cell once in and once
+// out (the tile margins come from L2), LDS takes the staged tile once and one
+// read per term and cell.
+RoundModel model_round_direct(const s5d_plan* p) {
+  RoundModel m;
+  const int nd = p->d.ndim, r = p->d.radius;
+  const int64_t w = p->elem;
+  double cells = 1, staged = 1;
+  int64_t tiles = 1;
+  // tile shape of the direct kernels: 2D 16 x 64, 3D 4 x 8 x (64, or 32 for r >= 3)
+  const int dims2[2] = {16, 64};
+  const int dims3[3] = {4, 8, r >= 3 ? 32 : 64};
+  for (int a = 0; a < nd; ++a) {
+    const int64_t I = p->d.interior[a];
+    const int D = nd == 2 ? dims2[a] : dims3[a];
+    const int64_t n = (I + D - 1) / D;
+    tiles *= n;
+    cells *= static_cast<double>(I);
+    staged *= static_cast<double>(D + 2 * r);
+  }
+  const double n_terms = static_cast<double>(p->coeffs.size());
+  m.gm = 2.0 * cells * w;
+  const double ops_term = p->kind == KIND_F32_COMP ? 9.0 : 1.0;
+  m.ops = cells * (n_terms * ops_term + 2.0) + static_cast<double>(tiles) * staged * 2.0;
+  m.lds = cells * n_terms * w + static_cast<double>(tiles) * staged * w;
+  m.wgs = tiles;
+  const Kernel2D& k2 = p->by_bt[1];
+  const Kernel3D& k3 = p->by_bt3[1];
+  const int occ = nd == 2 ? (k2.occupancy ? k2.occupancy() : 0) : (k3.occupancy ? k3.occupancy() : 0);
+  m.wg_per_cu = occ > 0 ? occ : 2;
+  return m;
+}
+
 RoundModel model_round3d(const s5d_plan* p, int bt) {
   RoundModel m;
   const Kernel3D& k = p->by_bt3[bt];
@@ -153,7 +186,11 @@ s5d_status model_plan(const s5d_plan* p, s5d_model* out) {
   for (size_t k = 0; k < rounds.size(); ++k) {
     const int bt = rounds[k];
     auto it = cache.find(bt);
-    if (it == cache.end()) it = cache.emplace(bt, p->d.ndim == 3 ? model_round3d(p, bt) : model_round2d(p, bt)).first;
+    if (it == cache.end())
+      it = cache
+               .emplace(bt, p->direct ? model_round_direct(p)
+                                      : (p->d.ndim == 3 ? model_round3d(p, bt) : model_round2d(p, bt)))
+               .first;
     const RoundModel& m = it->second;
     const double ta = m.ops / rt.valu, tg = m.gm / rt.hbm, tl = m.lds / rt.lds;
     // workgroup-slot efficiency: the launch runs in ceil(wgs / slots) waves
@@ -282,7 +319,20 @@ s5d_status s5d_autotune(const s5d_desc* desc, int32_t top_k, void* stream, s5d_t
   std::memset(&base_tun, 0, sizeof(base_tun));
   base_tun.struct_size = sizeof(s5d_tuning);
   (void)s5d_plan_query(base, &base_tun, nullptr);
+  const bool base_direct = base->direct;
   s5d_plan_destroy(base);
+  if (base_direct) {
+    // a direct kernel has no blocking parameters: nothing to choose
+    *best = base_tun;
+    if (report) {
+      report->n_candidates = 1;
+      report->n_measured = 0;
+      report->model_best_seconds = 0;
+      report->best_seconds_per_step = -1;
+      report->default_seconds_per_step = -1;
+    }
+    return S5D_OK;
+  }
 
   // enumerate: every compiled depth and tile family, a ladder of stream
   // block lengths plus the library's own choice (stream_chunk = 0)

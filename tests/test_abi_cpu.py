@@ -176,3 +176,24 @@ def test_error_norms_validation():
         st = lib.s5d_error_norms(*args, None)
         assert st == _lib.S5D_EINVAL, args
         assert _lib.last_error()
+
+
+def test_kernel_family_validation():
+    st, _ = _create(tuning=_lib.make_tuning(kernel=5))
+    assert st == _lib.S5D_EINVAL
+    # direct kernels take no blocking parameters
+    st, _ = _create(tuning=_lib.make_tuning(kernel="direct", bt=2))
+    assert st == _lib.S5D_EINVAL
+    # blocking asked for a stencil without a blocked variant
+    st, _ = _create(radius=3, box=True, tuning=_lib.make_tuning(kernel="blocked"))
+    assert st == _lib.S5D_EUNSUPPORTED
+
+
+def test_direct_plan_needs_a_device():
+    """A direct plan uploads its coefficient table at creation: without a GPU
+    that is a clean S5D_EDEVICE, never a crash."""
+    st, h = _create(radius=4, box=True)
+    if st == _lib.S5D_OK:  # a GPU is present
+        _lib.load().s5d_plan_destroy(h)
+    else:
+        assert st == _lib.S5D_EDEVICE, _lib.last_error()

@@ -39,22 +39,35 @@ def _small_mix(n, seed):
     return si.serve_mix(seed, n, rate_per_s=1.0, side2d=(40, 700), side3d=(12, 70), steps=(0, 40))
 
 
-def _serve(server, made, stagger=0):
-    """Submit (in waves of `stagger` requests per tick if > 0), tick to the end."""
+def _serve(server, made, stagger=0, fetch_each=False):
+    """Submit (all at once, or `stagger` requests per tick), tick until every
+    request is done; with fetch_each, fetch results as they finish (which
+    returns their memory to the budget).  Returns (ids, fetched results)."""
     t = torch()
-    ids = []
+    ids, outs = [], {}
+
+    def fetch_done():
+        for rid, (plan, g) in zip(ids, made):
+            if rid not in outs and server.request(rid)["state"] == 2:
+                outs[rid] = server.fetch(rid, np.empty_like(g))
+
     pending = list(range(len(made)))
-    while pending or server.tick()[0] or server.stats()["queued"]:
+    while True:
         take = pending if stagger <= 0 else pending[:stagger]
         for i in take:
             plan, g = made[i]
             init = t.from_numpy(g).to("cuda:0") if i % 2 else g  # device and host sources
             ids.append(server.submit(plan, init, keep_result=True))
         pending = pending[len(take):]
-        if stagger > 0:
-            server.tick()
+        running, queued = server.tick()
+        if fetch_each:
+            fetch_done()
+        if not pending and running == 0 and queued == 0:
+            break
     server.sync()
-    return ids
+    if fetch_each:
+        fetch_done()
+    return ids, outs
 
 
 @pytest.mark.parametrize("stagger", [0, 3])
@@ -63,7 +76,7 @@ def test_served_results_equal_alone(stagger):
     made = [_request(s) for s in specs]
     server = s5d.Server(hbm_budget_bytes=1 << 30)
     say("serve", len(specs), "requests, stagger", stagger)
-    ids = _serve(server, made, stagger)
+    ids, _ = _serve(server, made, stagger)
     st = server.stats()
     assert st["done"] == len(specs) and st["queued"] == 0 and st["running"] == 0
     for rid, (plan, g) in zip(ids, made):
@@ -89,14 +102,39 @@ def test_tight_budget_and_admission_order():
     budget = int(biggest * 1.5)
     server = s5d.Server(hbm_budget_bytes=budget)
     say("serve tight budget", budget)
-    ids = _serve(server, made)
+    ids, outs = _serve(server, made, fetch_each=True)
     st = server.stats()
-    assert st["bytes_peak"] <= budget and st["done"] == len(specs)
+    assert st["bytes_peak"] <= budget and st["done"] == len(specs) and st["bytes_in_use"] == 0
     admits = [server.request(r)["t_admit"] for r in ids]
     assert admits == sorted(admits)  # FIFO admission
     for rid, (plan, g) in zip(ids, made):
-        out = np.empty_like(g)
-        np.testing.assert_array_equal(server.fetch(rid, out), _alone(plan, g))
+        np.testing.assert_array_equal(outs[rid], _alone(plan, g))
+    server.close()
+
+
+def test_kept_results_hold_the_budget_until_fetched():
+    """Kept results keep their memory: with a budget for one request, the
+    second one waits (nothing running, one queued) until the first result is
+    fetched, then runs."""
+    specs = _small_mix(2, 95)
+    made = [_request(s) for s in specs]
+    budget = max(2 * g.nbytes for _, g in made)
+    server = s5d.Server(hbm_budget_bytes=budget)
+    ids = [server.submit(plan, g, keep_result=True) for plan, g in made]
+    for _ in range(10000):
+        running, queued = server.tick()
+        if running == 0:
+            break
+    server.sync()
+    assert server.tick() == (0, 1)  # blocked: the kept result holds the budget
+    assert server.request(ids[1])["state"] == 0
+    first = server.fetch(ids[0], np.empty_like(made[0][1]))
+    while server.tick() != (0, 0):
+        pass
+    server.sync()
+    second = server.fetch(ids[1], np.empty_like(made[1][1]))
+    np.testing.assert_array_equal(first, _alone(*made[0]))
+    np.testing.assert_array_equal(second, _alone(*made[1]))
     server.close()
 
 
@@ -104,7 +142,7 @@ def test_max_running_one_and_budget_error():
     specs = _small_mix(5, 93)
     made = [_request(s) for s in specs]
     server = s5d.Server(hbm_budget_bytes=1 << 30, max_running=1)
-    ids = _serve(server, made)
+    ids, _ = _serve(server, made)
     for rid, (plan, g) in zip(ids, made):
         out = np.empty_like(g)
         np.testing.assert_array_equal(server.fetch(rid, out), _alone(plan, g))
