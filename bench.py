@@ -197,13 +197,16 @@ def cpu_baseline(r, box, dtype, target_s=12.0):
     c = si.random_coeffs(rng, npts(r, box))
     g = rng.random(si.padded_shape((N, N), r)).astype(np.float32 if dtype == "f32" else np.float64)
     oracle.sweep(g, radius=r, box=box, coeffs=c, steps=1)  # warm-up: first touch of the pages
-    t0 = time.perf_counter()
-    oracle.sweep(g, radius=r, box=box, coeffs=c, steps=4)
-    one = (time.perf_counter() - t0) / 4
-    steps = int(max(2, min(T_STEPS, target_s / max(one, 1e-3))))
-    t0 = time.perf_counter()
-    oracle.sweep(g, radius=r, box=box, coeffs=c, steps=steps)
-    dt = time.perf_counter() - t0
+    # grow the sample until one run takes at least target_s (each call also
+    # copies the grid into its own two buffers, as the oracle always does)
+    steps = 8
+    while True:
+        t0 = time.perf_counter()
+        oracle.sweep(g, radius=r, box=box, coeffs=c, steps=steps)
+        dt = time.perf_counter() - t0
+        if dt >= target_s or steps >= T_STEPS:
+            break
+        steps = min(T_STEPS, int(steps * 1.15 * target_s / max(dt, 1e-3)) + 1)
     return {"value": N * N * steps / dt / 1e9, "unit": "GCell-updates/s",
             "cores": oracle.max_threads(), "kind": "oracle",
             "sample": "%s %s %dx%d interior, %d steps (of %d), %.1f s" % (
@@ -230,10 +233,46 @@ def full_sweep3d():
         s = time_steps(p, 1, 1)
         g = N3 ** 3 * T_STEPS / s / 1e9
         print(json.dumps({"stencil": name, "kind": KIND_NAMES[kind], "bt": bt,
-                          "tile": [nw * m, 64 * cpl],
+                          "tile": [nw * m, 64 * cpl], "kernel": "blocked",
                           "stream_chunk": p.info["stream_chunk"], "gcells": round(g, 1)}), flush=True)
         p.close()
         torch.cuda.empty_cache()
+    # the direct kernels (one step per launch) for every 3D stencil and kind
+    for kind in (0, 1, 2):
+        dtype, accum = KINDS[kind]
+        for r in (1, 2, 3, 4):
+            for box in (False, True):
+                name = "%s3d%dr" % ("box" if box else "star", r)
+                p = Problem(r, box, dtype, interior=(N3, N3, N3), accum=accum, kernel="direct",
+                            steps=100 if (box and r >= 3) else T_STEPS)
+                s = time_steps(p, 1, 1)
+                g = N3 ** 3 * p.steps / s / 1e9
+                print(json.dumps({"stencil": name, "kind": KIND_NAMES[kind], "bt": 1,
+                                  "kernel": "direct", "steps": p.steps, "gcells": round(g, 1)}),
+                      flush=True)
+                p.close()
+                torch.cuda.empty_cache()
+
+
+def sweep3d_default():
+    """Every 3D stencil of the synthetic suite at 512^3, T = 1000, default plan."""
+    import torch
+    out = []
+    for dtype in ("f32", "f64"):
+        for r, box in ((1, False), (2, False), (1, True), (2, True)):
+            p = Problem(r, box, dtype, interior=(N3, N3, N3))
+            s = time_steps(p, 1, 1)
+            g = N3 ** 3 * T_STEPS / s / 1e9
+            w = 4 if dtype == "f32" else 8
+            out.append({"stencil": "%s3d%dr" % ("box" if box else "star", r), "dtype": dtype,
+                        "bt": p.info["bt"], "kernel": ("auto", "blocked", "direct")[p.info["kernel"]],
+                        "tile": [p.info["tile0"], p.info["tile1"]], "gcells": g,
+                        "pct_hbm_bound": 100.0 * g * 2 * w / HBM_PEAK_GBS})
+            print("sweep3d %s %s bt=%d: %.1f GCell/s" % (out[-1]["stencil"], dtype, p.info["bt"], g),
+                  file=sys.stderr, flush=True)
+            p.close()
+            torch.cuda.empty_cache()
+    return out
 
 
 def full_sweep():
@@ -615,6 +654,7 @@ def main(argv=None):
                 print("bt-curve star2d1r %s bt=%d: %.1f GCell/s" % (dtype, bt, g),
                       file=sys.stderr, flush=True)
         rec["bt_curve_star2d1r"] = curve
+        rec["sweep3d_512"] = sweep3d_default()
     rec.update(extras)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(1, False, "f32")

@@ -69,12 +69,22 @@ const Entry3D* find3d(int kind, int box, int r, int cpl, int m, int nw, int bt) 
 
 // 3D defaults: the paper's scaling limits for 3D (star up to about 5, box up
 // to about 3 at radius 1; "Scaling Performance"), shallower at radius 2.
-int default_bt3(int kind, int box, int r) {
-  // compensated accumulation is bound by arithmetic from the first level on
-  if (kind == KIND_F32_COMP) return 1;
-  if (r == 1) return box ? 3 : 4;
-  return box ? 1 : 2;
+// 3D defaults: depth and rows per wave (tile family), the best pair measured
+// on MI355X at 512^3, T = 1000.  Compensated accumulation is bound by
+// arithmetic from the first level on.
+struct Default3D {
+  int bt, m;
+};
+Default3D default_tuning3(int kind, int box, int r) {
+  if (kind == KIND_F32_COMP) return {1, 2};
+  if (kind == KIND_F64) {
+    if (r == 1) return box ? Default3D{2, 4} : Default3D{3, 2};
+    return box ? Default3D{1, 2} : Default3D{2, 2};
+  }
+  if (r == 1) return box ? Default3D{2, 4} : Default3D{3, 4};
+  return box ? Default3D{1, 4} : Default3D{2, 4};
 }
+int default_bt3(int kind, int box, int r) { return default_tuning3(kind, box, r).bt; }
 
 // Is any blocked variant compiled for this stencil?
 bool has_blocked(int kind, int ndim, int box, int r) {
@@ -322,11 +332,20 @@ s5d_status plan_3d(s5d_plan* p, const s5d_tuning& req, int box, int r) {
   // this stencil; explicit fields must match one of them
   const Entry3D* fam = nullptr;
   int bt_cap = 0;
+  // without an explicit shape, the default family if it is built
+  int want_m = req.rows_per_wave;
+  if (want_m == 0 && req.cells_per_lane == 0 && req.tile0 == 0 && req.tile1 == 0) {
+    const int m = default_tuning3(p->kind, box, r).m;
+    for (int i = 0; i < s5d::kRegistry3DSize && want_m == 0; ++i) {
+      const Entry3D& e = s5d::kRegistry3D[i];
+      if (e.dtype == p->kind && e.box == box && e.r == r && e.m == m) want_m = m;
+    }
+  }
   for (int i = 0; i < s5d::kRegistry3DSize; ++i) {
     const Entry3D& e = s5d::kRegistry3D[i];
     if (e.dtype != p->kind || e.box != box || e.r != r) continue;
     if (req.cells_per_lane > 0 && e.cpl != req.cells_per_lane) continue;
-    if (req.rows_per_wave > 0 && e.m != req.rows_per_wave) continue;
+    if (want_m > 0 && e.m != want_m) continue;
     if (req.tile0 > 0 && e.m * e.nw != req.tile0) continue;
     if (req.tile1 > 0 && 64 * e.cpl != req.tile1) continue;
     if (!fam || (e.cpl == fam->cpl && e.m == fam->m && e.nw == fam->nw)) {
