@@ -408,6 +408,7 @@ def bench_serve(n_requests=32, loads=(0.8,), budgets=(64 << 30,)):
         t0 = srv.now()
         order = sorted(range(len(plans)), key=lambda i: arrivals[i])
         k = 0
+        reported = ticks = 0
         while True:
             now = srv.now() - t0
             while k < len(order) and arrivals[order[k]] <= now:
@@ -415,6 +416,13 @@ def bench_serve(n_requests=32, loads=(0.8,), budgets=(64 << 30,)):
                 srv.submit(plans[i], inits[i], arrival=t0 + arrivals[i])
                 k += 1
             running, queued = srv.tick()
+            ticks += 1
+            if ticks % 64 == 0:
+                done = srv.stats()["done"]
+                if done >= reported + max(4, len(order) // 8):
+                    reported = done
+                    print("serve: %d of %d requests done" % (done, len(order)), file=sys.stderr,
+                          flush=True)
             if running == 0 and queued == 0:
                 if k == len(order):
                     break
@@ -426,10 +434,11 @@ def bench_serve(n_requests=32, loads=(0.8,), budgets=(64 << 30,)):
 
     # plain: every request alone, one after the other
     t = time.perf_counter()
-    for p, x in zip(plans, inits):
+    for j, (p, x) in enumerate(zip(plans, inits)):
         y = torch.empty_like(x)
         p.run(x.clone(), y)
         torch.cuda.synchronize()
+        print("plain: request %d done" % j, file=sys.stderr, flush=True)
     plain = time.perf_counter() - t
     out["plain_sequential_gcells"] = sum(updates) / plain / 1e9
     cap = serve([0.0] * len(plans), budgets[0])

@@ -257,6 +257,10 @@ typedef struct s5d_server_config {
     uint32_t struct_size;     /* = sizeof(s5d_server_config) */
     int32_t max_running;      /* requests running at once; 0 = no limit */
     int64_t hbm_budget_bytes; /* device memory for the grids of admitted requests */
+    int32_t rounds_per_tick;  /* rounds of each running request per tick; 0 = adaptive:
+                                 ceil(8 / running), at most 16, so that a tick carries
+                                 enough launches while few requests run */
+    int32_t reserved;
 } s5d_server_config;
 
 /* Request states. */
@@ -306,7 +310,7 @@ s5d_status s5d_server_now(const s5d_server *server, double *seconds);
 s5d_status s5d_server_submit(s5d_server *server, const s5d_plan *plan, const void *init,
                              double arrival, int32_t keep_result, int64_t *id);
 
-/* One tick (see above).  n_running / n_queued (may be NULL) receive the
+/* One tick (see above; with rounds_per_tick != 1, step 2 repeats).  n_running / n_queued (may be NULL) receive the
  * counts after it.  n_running = 0 with n_queued > 0 means the next queued
  * request does not fit beside the kept results: it waits until they are
  * fetched. */

@@ -235,12 +235,13 @@ class Server:
     are admitted under an HBM budget and advance one round per ``tick()``,
     all running requests together.  Times are seconds on the server clock."""
 
-    def __init__(self, *, hbm_budget_bytes, max_running=0):
+    def __init__(self, *, hbm_budget_bytes, max_running=0, rounds_per_tick=0):
         lib = _lib.load()
         cfg = _lib.S5DServerConfig()
         cfg.struct_size = ctypes.sizeof(cfg)
         cfg.max_running = int(max_running)
         cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        cfg.rounds_per_tick = int(rounds_per_tick)
         h = ctypes.c_void_p()
         _lib.check(lib.s5d_server_create(ctypes.byref(cfg), ctypes.byref(h)), "s5d_server_create")
         self._h = h
@@ -307,9 +308,11 @@ class Server:
         return {k: getattr(st, k) for k, _ in st._fields_ if k not in ("struct_size", "reserved")}
 
     def _drop_admitted(self):
-        for rid in list(self._inits):
-            if self.request(rid)["state"] != _lib.REQ_QUEUED:
-                del self._inits[rid]
+        # admission is FIFO: stop at the first request still queued
+        for rid in sorted(self._inits):
+            if self.request(rid)["state"] == _lib.REQ_QUEUED:
+                break
+            del self._inits[rid]
 
     def close(self):
         if getattr(self, "_h", None) is not None:

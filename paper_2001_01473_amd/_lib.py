@@ -55,7 +55,8 @@ class S5DTuning(ctypes.Structure):
 
 class S5DServerConfig(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("max_running", ctypes.c_int32),
-                ("hbm_budget_bytes", ctypes.c_int64)]
+                ("hbm_budget_bytes", ctypes.c_int64), ("rounds_per_tick", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class S5DRequestInfo(ctypes.Structure):

@@ -30,6 +30,11 @@
 namespace {
 
 constexpr int kSlots = 3;
+// With few requests running, a tick enqueues several rounds of each so that
+// it holds about this many launches (the host's per-tick work is then spread
+// over more GPU work); at most kMaxRoundsPerTick.
+constexpr int kTargetLaunches = 8;
+constexpr int kMaxRoundsPerTick = 16;
 
 struct Request {
   int64_t id = 0;
@@ -129,6 +134,20 @@ s5d_status retire(s5d_server* s) {
   return S5D_OK;
 }
 
+// Mark `reqs` as finishing once the work enqueued so far completes; results
+// that are not kept give their memory back (stream-ordered).
+s5d_status record_finish(s5d_server* s, const std::vector<Request*>& reqs) {
+  hipEvent_t ev = nullptr;
+  const s5d_status st = take_event(s, &ev);
+  if (st != S5D_OK) return st;
+  const hipError_t e = hipEventRecord(ev, s->stream);
+  if (e != hipSuccess) return device_fail(e, "hipEventRecord");
+  for (Request* r : reqs)
+    if (!r->keep) release_buffers(s, r);
+  s->finishing.push_back(Finishing{ev, reqs});
+  return S5D_OK;
+}
+
 s5d_status admit(s5d_server* s, Request* r) {
   const int64_t nb = r->plan.bytes;
   for (int i = 0; i < 2; ++i) {
@@ -220,6 +239,8 @@ s5d_status s5d_server_create(const s5d_server_config* config, s5d_server** out) 
   if (config->struct_size < sizeof(s5d_server_config)) return fail(S5D_EINVAL, "config->struct_size too small");
   if (config->hbm_budget_bytes <= 0) return fail(S5D_EINVAL, "hbm_budget_bytes must be > 0");
   if (config->max_running < 0) return fail(S5D_EINVAL, "max_running must be >= 0");
+  if (config->rounds_per_tick < 0 || config->rounds_per_tick > 1024)
+    return fail(S5D_EINVAL, "rounds_per_tick must be in 0..1024");
   s5d_server* s = new (std::nothrow) s5d_server;
   if (!s) return fail(S5D_ENOMEM, "server allocation failed");
   s->cfg = *config;
@@ -291,7 +312,6 @@ s5d_status s5d_server_tick(s5d_server* s, int32_t* n_running, int32_t* n_queued)
   s5d_status st = retire(s);
   if (st != S5D_OK) return st;
   // 1. admission, FIFO under the budget
-  hipEvent_t fin_ev = nullptr;
   std::vector<Request*> fin;
   while (!s->queue.empty()) {
     Request* r = s->queue.front();
@@ -307,18 +327,41 @@ s5d_status s5d_server_tick(s5d_server* s, int32_t* n_running, int32_t* n_queued)
     else
       s->running.push_back(r);
   }
-  // 2. one round of every running request
-  if (!s->running.empty()) {
-    std::vector<s5d::RoundItem> items;
-    items.reserve(s->running.size());
-    for (Request* r : s->running) {
-      const size_t k = r->next++;
-      items.push_back(s5d::RoundItem{&r->plan, r->rounds[k], r->buf[k % 2], r->buf[(k + 1) % 2]});
-    }
-    std::vector<unsigned char> blob;
-    std::vector<s5d::GroupLaunch> launches;
-    st = s5d::build_step(items, blob, launches);
+  // requests of zero steps finish at admission
+  if (!fin.empty()) {
+    st = record_finish(s, fin);
     if (st != S5D_OK) return st;
+    fin.clear();
+  }
+  // 2. one round (or a few, while few requests run) of every running request
+  if (!s->running.empty()) {
+    const int n = static_cast<int>(s->running.size());
+    const int K = s->cfg.rounds_per_tick > 0
+                      ? s->cfg.rounds_per_tick
+                      : std::min(kMaxRoundsPerTick, std::max(1, (kTargetLaunches + n - 1) / n));
+    std::vector<unsigned char> blob;
+    std::vector<std::vector<s5d::GroupLaunch>> steps;
+    std::vector<std::vector<Request*>> fin_after;  // requests whose last round is in step j
+    for (int j = 0; j < K && !s->running.empty(); ++j) {
+      std::vector<s5d::RoundItem> items;
+      items.reserve(s->running.size());
+      for (Request* r : s->running) {
+        const size_t k = r->next++;
+        items.push_back(s5d::RoundItem{&r->plan, r->rounds[k], r->buf[k % 2], r->buf[(k + 1) % 2]});
+      }
+      steps.emplace_back();
+      st = s5d::build_step(items, blob, steps.back());
+      if (st != S5D_OK) return st;
+      fin_after.emplace_back();
+      std::vector<Request*> still;
+      for (Request* r : s->running) {
+        if (r->next == r->rounds.size())
+          fin_after.back().push_back(r);
+        else
+          still.push_back(r);
+      }
+      s->running.swap(still);
+    }
     Slot& sl = s->slots[s->ticks % kSlots];
     if (sl.pending) {
       const hipError_t e = hipEventSynchronize(sl.ev);  // paces the host: at most kSlots ticks in flight
@@ -330,30 +373,19 @@ s5d_status s5d_server_tick(s5d_server* s, int32_t* n_running, int32_t* n_queued)
     std::memcpy(sl.host, blob.data(), blob.size());
     hipError_t e = hipMemcpyAsync(sl.dev, sl.host, blob.size(), hipMemcpyHostToDevice, s->stream);
     if (e != hipSuccess) return device_fail(e, "tick table upload");
-    e = s5d::enqueue_step(launches, sl.dev, s->stream);
-    if (e != hipSuccess) return device_fail(e, "tick launch");
+    for (size_t j = 0; j < steps.size(); ++j) {
+      e = s5d::enqueue_step(steps[j], sl.dev, s->stream);
+      if (e != hipSuccess) return device_fail(e, "tick launch");
+      s->launches += static_cast<int64_t>(steps[j].size());
+      if (!fin_after[j].empty()) {
+        st = record_finish(s, fin_after[j]);
+        if (st != S5D_OK) return st;
+      }
+    }
     e = hipEventRecord(sl.ev, s->stream);
     if (e != hipSuccess) return device_fail(e, "hipEventRecord");
     sl.pending = true;
     ++s->ticks;
-    s->launches += static_cast<int64_t>(launches.size());
-    std::vector<Request*> still;
-    for (Request* r : s->running) {
-      if (r->next == r->rounds.size())
-        fin.push_back(r);
-      else
-        still.push_back(r);
-    }
-    s->running.swap(still);
-  }
-  if (!fin.empty()) {
-    st = take_event(s, &fin_ev);
-    if (st != S5D_OK) return st;
-    const hipError_t e = hipEventRecord(fin_ev, s->stream);
-    if (e != hipSuccess) return device_fail(e, "hipEventRecord");
-    for (Request* r : fin)
-      if (!r->keep) release_buffers(s, r);
-    s->finishing.push_back(Finishing{fin_ev, fin});
   }
   if (n_running) *n_running = static_cast<int32_t>(s->running.size());
   if (n_queued) *n_queued = static_cast<int32_t>(s->queue.size());
