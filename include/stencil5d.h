@@ -29,12 +29,14 @@
  *
  * How it is computed (AN5D, "Execution Model" and "Optimizations"): each GPU
  * launch advances b_T time steps at once.  A tile of the plane normal to axis
- * 0 streams along axis 0 and keeps, per fused time level, a window of
- * 2*radius+1 planes in registers; the tile overlaps its neighbours by
- * b_T*radius cells on each side and only its compute region is stored.  The
- * result equals the plain loop up to the rounding of the fused multiply-adds
- * the kernels use (float64: relative error far below 1e-12 for the workloads
- * in the test-suite).
+ * 0 streams along axis 0; every arriving plane is pushed into the 2*radius+1
+ * output planes it feeds, so each fused time level holds 2*radius partial
+ * sums in registers.  The tile overlaps its neighbours by b_T*radius cells on
+ * each side and only its compute region is stored.  Every output sums its
+ * terms in the canonical order above, so the result equals the plain loop up
+ * to the rounding of the fused multiply-adds the kernels use (float64:
+ * relative error far below 1e-12 for the workloads in the test-suite), and
+ * every blocking choice gives the same bits.
  */
 #ifndef STENCIL5D_H
 #define STENCIL5D_H
