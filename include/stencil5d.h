@@ -148,9 +148,11 @@ s5d_status s5d_run(const s5d_plan *plan, void *buf0, void *buf1, void *stream,
  * compute every fused level; lanes outside the grid move no data; LDS carries
  * the 3D edge-row exchange), divide each by the device's rate (VALU 64
  * lane-operations per clock per CU, HBM 6.0e12 B/s sustained, LDS 128 B per
- * clock per CU), take the largest and divide by the workgroup-slot
- * efficiency (the fraction of resident-workgroup slots the launch's waves of
- * workgroups fill).  The whole sweep is the sum over its rounds. */
+ * clock per CU), take the largest and divide by the slot efficiency
+ * 1 / (max(1, s/g) + 0.75 min(1, s/g)) for g workgroups and s resident slots
+ * (an idle part of the machine when g < s, else a tail of about 0.75
+ * workgroup durations as the last ones finish unevenly).  The whole sweep is
+ * the sum over its rounds. */
 typedef struct s5d_model {
     uint32_t struct_size; /* = sizeof(s5d_model) */
     int32_t bound;        /* largest term of the first round's kind: 0 ALU, 1 HBM, 2 LDS */

@@ -67,8 +67,6 @@ const Entry3D* find3d(int kind, int box, int r, int cpl, int m, int nw, int bt) 
   return nullptr;
 }
 
-// 3D defaults: the paper's scaling limits for 3D (star up to about 5, box up
-// to about 3 at radius 1; "Scaling Performance"), shallower at radius 2.
 // 3D defaults: depth and rows per wave (tile family), the best pair measured
 // on MI355X at 512^3, T = 1000.  Compensated accumulation is bound by
 // arithmetic from the first level on.
@@ -126,7 +124,7 @@ int max_bt2d(int kind, int box, int r, int cpl) {
 }
 
 // Defaults when the caller leaves b_T and the cells per lane to the library:
-// the best pair measured on MI355X at 16384^2, T = 1000, per (dtype, shape,
+// the best pair the autotuner measured on MI355X at 16384^2, per (kind, shape,
 // radius).  Low-order stencils take deep temporal blocking (AN5D "Scaling
 // Performance"); high-order and box stencils shallower, where the per-level
 // work and the register window grow.
@@ -134,12 +132,12 @@ struct Default2D {
   int bt, cpl;
 };
 Default2D default_tuning(int kind, int box, int r) {
-  static const Default2D f32_star[4] = {{10, 4}, {7, 4}, {4, 4}, {3, 4}};
-  static const Default2D f32_box[2] = {{6, 4}, {3, 4}};
-  static const Default2D f64_star[4] = {{9, 2}, {4, 2}, {3, 4}, {2, 4}};
-  static const Default2D f64_box[2] = {{8, 2}, {3, 2}};
-  static const Default2D comp_star[4] = {{3, 4}, {2, 4}, {2, 4}, {1, 4}};
-  static const Default2D comp_box[2] = {{2, 4}, {1, 4}};
+  static const Default2D f32_star[4] = {{10, 4}, {7, 4}, {5, 4}, {3, 4}};
+  static const Default2D f32_box[2] = {{7, 4}, {3, 4}};
+  static const Default2D f64_star[4] = {{10, 2}, {6, 2}, {3, 4}, {2, 4}};
+  static const Default2D f64_box[2] = {{8, 2}, {4, 2}};
+  static const Default2D comp_star[4] = {{3, 4}, {1, 4}, {1, 4}, {1, 4}};
+  static const Default2D comp_box[2] = {{1, 4}, {1, 4}};
   if (kind == KIND_F32) return box ? f32_box[r - 1] : f32_star[r - 1];
   if (kind == KIND_F32_COMP) return box ? comp_box[r - 1] : comp_star[r - 1];
   return box ? f64_box[r - 1] : f64_star[r - 1];
@@ -168,21 +166,25 @@ DeviceInfo query_device() {
   return d;
 }
 
-// Stream-block length h_SN from an occupancy model (AN5D "Performance Model",
-// SM efficiency): waves run in rounds of `slots`; a block of h rows costs
-// h + 2*b_T*r steps (warm-up and drain of the fused levels).  Minimise
-// ceil(waves / slots) * (h + 2*b_T*r).
+// Stream-block length h_SN (AN5D "Division of Streaming Dimension" and the
+// SM efficiency of its "Performance Model"): a block of h rows costs
+// h + 2*b_T*r row-steps (the warm-up and drain of the fused levels); the
+// launch takes the blocks' total work spread over `slots` resident units plus
+// a tail of about kTail block durations, as the last blocks finish unevenly
+// (measured on MI355X: many short blocks beat one wave of long ones).
+// Minimise  max(blocks / slots, 1) * (h + 2 b_T r) + kTail * (h + 2 b_T r).
+constexpr double kTail = 0.75;
+
 int choose_chunk(int64_t I0, int64_t ntiles, int64_t slots, int bt, int r) {
-  const int64_t hmin = std::max<int64_t>(16, 4LL * bt * r);
+  const int64_t hmin = std::max<int64_t>(8, static_cast<int64_t>(bt) * r);
   int64_t best_h = I0;
   double best_cost = 1e300;
   const int64_t max_nch = std::max<int64_t>(1, I0 / hmin);
   for (int64_t nch = 1; nch <= max_nch && nch <= 65536; ++nch) {
     const int64_t h = (I0 + nch - 1) / nch;
-    const int64_t nch_eff = (I0 + h - 1) / h;
-    const int64_t waves = ntiles * nch_eff;
-    const int64_t rounds = (waves + slots - 1) / slots;
-    const double cost = static_cast<double>(rounds) * static_cast<double>(h + 2LL * bt * r);
+    const int64_t blocks = ntiles * ((I0 + h - 1) / h);
+    const double per = static_cast<double>(h + 2LL * bt * r);
+    const double cost = std::max(static_cast<double>(blocks) / static_cast<double>(slots), 1.0) * per + kTail * per;
     if (cost < best_cost * (1.0 - 1e-9)) {
       best_cost = cost;
       best_h = h;
@@ -319,7 +321,7 @@ s5d_status plan_2d(s5d_plan* p, const s5d_tuning& req, int box, int r) {
     const DeviceInfo dev = query_device();
     int occ = dev.ok ? p->by_bt[bt].occupancy() : 0;
     if (occ <= 0) occ = 2;
-    const int64_t C = 64LL * cpl - 2LL * bt * r;
+    const int64_t C = s5d::compute_width(64 * cpl, bt, r, p->elem);
     const int64_t ntiles = (d.interior[1] + C - 1) / C;
     const int64_t slots = static_cast<int64_t>(dev.cus) * occ * s5d::kWavesPerBlock;
     chunk = choose_chunk(d.interior[0], ntiles, slots, bt, r);
@@ -376,7 +378,7 @@ s5d_status plan_3d(s5d_plan* p, const s5d_tuning& req, int box, int r) {
     const DeviceInfo dev = query_device();
     int occ = dev.ok ? p->by_bt3[bt].occupancy() : 0;
     if (occ <= 0) occ = 1;
-    const int64_t C1 = B1 - 2LL * bt * r, C2 = B2 - 2LL * bt * r;
+    const int64_t C1 = B1 - 2LL * bt * r, C2 = s5d::compute_width(B2, bt, r, p->elem);
     const int64_t ntiles = ((d.interior[1] + C1 - 1) / C1) * ((d.interior[2] + C2 - 1) / C2);
     const int64_t slots = static_cast<int64_t>(dev.cus) * occ;  // resident workgroups
     chunk = choose_chunk(d.interior[0], ntiles, slots, bt, r);

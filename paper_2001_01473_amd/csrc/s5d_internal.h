@@ -12,6 +12,27 @@ constexpr int npts(int ndim, int r, bool box) {
              : 2 * r * ndim + 1;
 }
 
+// Columns of overlap on the left and right of a tile (the last axis): at
+// least bt*r each (the valid width shrinks by r per side and level), chosen so
+// that the tile's first column and the compute width are multiples of
+// 16 bytes / elem: with the tile at column R + t*C - left, every tile then
+// starts on the same 16-byte phase of its row, 0 when the row pitch is a
+// multiple of 16 bytes, so the lanes' vector loads are aligned.
+constexpr int overlap_left(int bt, int r, int elem) {
+  int x = bt * r;
+  while ((x - r) % (16 / elem) != 0) ++x;
+  return x;
+}
+constexpr int overlap_right(int bt, int r, int elem) {
+  int y = bt * r;
+  while ((overlap_left(bt, r, elem) + y) % (16 / elem) != 0) ++y;
+  return y;
+}
+// Compute-region width of a tile of w columns.
+constexpr int compute_width(int w, int bt, int r, int elem) {
+  return w - overlap_left(bt, r, elem) - overlap_right(bt, r, elem);
+}
+
 // Coefficients travel by value in the kernel arguments, so they are loaded
 // into scalar registers once per wave and feed every FMA as an SGPR operand.
 template <typename T, int N>

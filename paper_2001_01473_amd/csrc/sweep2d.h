@@ -62,7 +62,10 @@ __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPac
   constexpr int NA = 2 * R;         // pending output rows per level
   constexpr int NS = lcm_i(NA, NR); // steps per unrolled iteration (NR: rows in the load ring)
   constexpr int W = 64 * CPL;       // tile width (columns)
-  constexpr int C = W - 2 * BT * R; // compute-region width
+  constexpr int LO = overlap_left(BT, R, sizeof(T));  // overlap columns on the left
+  constexpr int C = compute_width(W, BT, R, sizeof(T)); // compute-region width
+  // the compute region is whole lanes when it starts and ends on lane edges
+  constexpr bool WHOLE = LO % CPL == 0 && C % CPL == 0;
   constexpr int MCOL = BT * R + 1;  // rows kept in the boundary-column stash
   constexpr int XL = CPL + 2 * R;   // extended row: R cells of lane-1 | own CPL | R cells of lane+1
   constexpr uint32_t WB = sizeof(T);
@@ -70,14 +73,16 @@ __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPac
   const int I0 = a.I0, I1 = a.I1;
   const int P0 = I0 + 2 * R, P1 = I1 + 2 * R;
   const int c_first = R + tile * C;      // first compute column
-  const int col0 = c_first - BT * R;     // first column of the tile
+  const int col0 = c_first - LO;         // first column of the tile
   const int row_a = R + chunk * a.chunk; // first output row of this stream block
   const int row_b = min(row_a + a.chunk, I0 + R);
   const int colL = col0 + lane * CPL;    // first column owned by this lane
 
   // Stores: a lane whose CPL cells all lie in the compute region writes them
-  // as one vector (vstore); the few lanes that straddle its edge write cell by
-  // cell (soff).  Out-of-range offsets make the other path a no-op.
+  // as one vector (vstore); a lane that straddles its edge writes cell by cell
+  // (soff).  When the region is whole lanes, only a tile that reaches the
+  // grid's last column (an EDGE wave) has such a lane.  Out-of-range offsets
+  // make the unused path a no-op.
   uint32_t soff[CPL];
   bool full = true;
   sfor<CPL>([&](auto K) S5D_INL {
@@ -229,7 +234,7 @@ __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPac
           const auto rs = make_rsrc(dst + static_cast<int64_t>(keep ? o : row_a) * P1,
                                     keep ? static_cast<uint32_t>(P1) * WB : 0u);
           buf_store_lane(out, rs, vstore);
-          sfor<CPL>([&](auto K) S5D_INL { buf_store(out[K], rs, soff[K]); });
+          if constexpr (EDGE || !WHOLE) sfor<CPL>([&](auto K) S5D_INL { buf_store(out[K], rs, soff[K]); });
         }
       });
     });
@@ -246,7 +251,8 @@ template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
 __device__ __forceinline__ void sweep2d_block(const Sweep2DArgs& a, const CoefPack<T, npts(2, R, BOX)>& cf, int lb,
                                               EdgeStash<T, R, BT, CPL>* stash) {
   constexpr int W = 64 * CPL;
-  constexpr int C = W - 2 * BT * R;
+  constexpr int LO = overlap_left(BT, R, sizeof(T));
+  constexpr int C = compute_width(W, BT, R, sizeof(T));
   static_assert(R <= CPL, "the lane exchange reaches one neighbouring lane only");
   static_assert(C >= 1, "tile narrower than its overlap");
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -257,7 +263,7 @@ __device__ __forceinline__ void sweep2d_block(const Sweep2DArgs& a, const CoefPa
   const int chunk = wid / a.ntiles;
 
   const int P1 = a.I1 + 2 * R;
-  const int col0 = R + tile * C - BT * R;
+  const int col0 = R + tile * C - LO;
   const int row_a = R + chunk * a.chunk;
   const int row_b = min(row_a + a.chunk, a.I0 + R);
   const bool edge = col0 < 0 || col0 + W > P1 || row_a - (BT - 1) * R < R ||
@@ -299,7 +305,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void sweep2d_batch_kernel(
 template <typename T, int R, bool BOX, int BT, int CPL>
 Sweep2DArgs make_args2d(const Round2D& rd, CoefPack<T, npts(2, R, BOX)>& cf) {
   constexpr int NP = npts(2, R, BOX);
-  constexpr int C = 64 * CPL - 2 * BT * R;
+  constexpr int C = compute_width(64 * CPL, BT, R, sizeof(T));
   for (int k = 0; k < NP; ++k) cf.c[k] = static_cast<T>(rd.coeffs[k]);
   Sweep2DArgs a;
   a.src = rd.src;

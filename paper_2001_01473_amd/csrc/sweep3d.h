@@ -40,7 +40,9 @@ __device__ __forceinline__ void sweep3d_body(const Sweep3DArgs& a, const CoefPac
   constexpr int B1 = NW * M;         // tile rows (axis 1)
   constexpr int B2 = 64 * CPL;       // tile columns (axis 2)
   constexpr int C1 = B1 - 2 * BT * R;
-  constexpr int C2 = B2 - 2 * BT * R;
+  constexpr int LO2 = overlap_left(BT, R, sizeof(T));  // column overlap on the left
+  constexpr int C2 = compute_width(B2, BT, R, sizeof(T));
+  constexpr bool WHOLE = LO2 % CPL == 0 && C2 % CPL == 0;  // compute columns are whole lanes
   constexpr int XR = M + 2 * R;      // extended rows: R from wave w-1 | own M | R from wave w+1
   constexpr int XL = CPL + 2 * R;    // extended columns
   constexpr uint32_t WB = sizeof(T);
@@ -50,7 +52,7 @@ __device__ __forceinline__ void sweep3d_body(const Sweep3DArgs& a, const CoefPac
   const int P0 = I0 + 2 * R, P1 = I1 + 2 * R, P2 = I2 + 2 * R;
   const int r_first = R + t1 * C1, c_first = R + t2 * C2;
   const int row0 = r_first - BT * R + w * M;  // first row held by this wave
-  const int colL = c_first - BT * R + lane * CPL;
+  const int colL = c_first - LO2 + lane * CPL;
   const int pl_a = R + chunk * a.chunk;        // output planes of this stream block
   const int pl_b = min(pl_a + a.chunk, I0 + R);
 
@@ -241,7 +243,8 @@ __device__ __forceinline__ void sweep3d_body(const Sweep3DArgs& a, const CoefPac
             const auto rs = make_rsrc(row_ptr(dst, keep ? o : pl_a, keep ? row0 + MI : r_first),
                                       keep ? static_cast<uint32_t>(P2) * WB : 0u);
             buf_store_lane(out[MI], rs, vstore);
-            sfor<CPL>([&](auto K) S5D_INL { buf_store(out[MI][K], rs, soff[K]); });
+            // lanes straddling the compute region's edge store cell by cell
+            if constexpr (EDGE || !WHOLE) sfor<CPL>([&](auto K) S5D_INL { buf_store(out[MI][K], rs, soff[K]); });
           });
         }
       });
@@ -256,7 +259,7 @@ template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int M, int NW, 
 __device__ __forceinline__ void sweep3d_block(const Sweep3DArgs& a, const CoefPack<T, npts(3, R, BOX)>& cf, int lb,
                                               T (&xbuf)[2][NW][2 * R][64 * CPL]) {
   constexpr int B1 = NW * M, B2 = 64 * CPL;
-  constexpr int C1 = B1 - 2 * BT * R, C2 = B2 - 2 * BT * R;
+  constexpr int C1 = B1 - 2 * BT * R, C2 = compute_width(B2, BT, R, sizeof(T));
   static_assert(R <= CPL, "the lane exchange reaches one neighbouring lane only");
   static_assert(C1 >= 1 && C2 >= 1, "tile narrower than its overlap");
   const int t2 = lb % a.nt2;
@@ -266,7 +269,7 @@ __device__ __forceinline__ void sweep3d_block(const Sweep3DArgs& a, const CoefPa
   const int lane = threadIdx.x & 63;
 
   const int P1 = a.I1 + 2 * R, P2 = a.I2 + 2 * R;
-  const int row0 = R + t1 * C1 - BT * R, col0 = R + t2 * C2 - BT * R;
+  const int row0 = R + t1 * C1 - BT * R, col0 = R + t2 * C2 - overlap_left(BT, R, sizeof(T));
   const int pl_a = R + chunk * a.chunk;
   const int pl_b = min(pl_a + a.chunk, a.I0 + R);
   const bool edge = row0 < 0 || row0 + B1 > P1 || col0 < 0 || col0 + B2 > P2 ||
@@ -307,7 +310,7 @@ __global__ __launch_bounds__(64 * NW) void sweep3d_batch_kernel(const Item3D<T, 
 template <typename T, int R, bool BOX, int BT, int CPL, int M, int NW>
 int64_t make_args3d(const Round3D& rd, Sweep3DArgs& a, CoefPack<T, npts(3, R, BOX)>& cf) {
   constexpr int NP = npts(3, R, BOX);
-  constexpr int C1 = NW * M - 2 * BT * R, C2 = 64 * CPL - 2 * BT * R;
+  constexpr int C1 = NW * M - 2 * BT * R, C2 = compute_width(64 * CPL, BT, R, sizeof(T));
   for (int k = 0; k < NP; ++k) cf.c[k] = static_cast<T>(rd.coeffs[k]);
   a.src = rd.src;
   a.dst = rd.dst;

@@ -70,6 +70,9 @@ double ops_per_cell(const s5d_plan* p, int cpl) {
   return ops;
 }
 
+// Tail of a launch in workgroup durations (as in the stream-block chooser).
+constexpr double kTail = 0.75;
+
 // Rows [a, b) clipped to [0, n).
 int64_t clip(int64_t a, int64_t b, int64_t n) { return std::max<int64_t>(0, std::min(b, n) - std::max<int64_t>(a, 0)); }
 
@@ -81,14 +84,15 @@ struct RoundModel {
 
 RoundModel model_round2d(const s5d_plan* p, int bt) {
   RoundModel m;
-  const int r = p->d.radius, cpl = p->tun.cells_per_lane, W = 64 * cpl, C = W - 2 * bt * r;
+  const int r = p->d.radius, cpl = p->tun.cells_per_lane, W = 64 * cpl;
+  const int LO = overlap_left(bt, r, p->elem), C = compute_width(W, bt, r, p->elem);
   const int64_t I0 = p->d.interior[0], I1 = p->d.interior[1], P0 = I0 + 2 * r, P1 = I1 + 2 * r;
   const int64_t h = p->tun.stream_chunk, w = p->elem;
   const int64_t ntiles = (I1 + C - 1) / C, nch = (I0 + h - 1) / h;
   int64_t cols_read = 0, cols_written = 0;
   for (int64_t t = 0; t < ntiles; ++t) {
     const int64_t c0 = r + t * C;
-    cols_read += clip(c0 - static_cast<int64_t>(bt) * r, c0 - static_cast<int64_t>(bt) * r + W, P1);
+    cols_read += clip(c0 - LO, c0 - LO + W, P1);
     cols_written += std::min<int64_t>(C, I1 - t * C);
   }
   double rows_read = 0, rows_comp = 0;
@@ -142,7 +146,8 @@ RoundModel model_round3d(const s5d_plan* p, int bt) {
   RoundModel m;
   const Kernel3D& k = p->by_bt3[bt];
   const int r = p->d.radius, cpl = k.cpl, B1 = k.nw * k.m, B2 = 64 * cpl;
-  const int C1 = B1 - 2 * bt * r, C2 = B2 - 2 * bt * r;
+  const int LO2 = overlap_left(bt, r, p->elem);
+  const int C1 = B1 - 2 * bt * r, C2 = compute_width(B2, bt, r, p->elem);
   const int64_t I0 = p->d.interior[0], I1 = p->d.interior[1], I2 = p->d.interior[2];
   const int64_t P0 = I0 + 2 * r, P1 = I1 + 2 * r, P2 = I2 + 2 * r;
   const int64_t h = p->tun.stream_chunk, w = p->elem;
@@ -154,7 +159,7 @@ RoundModel model_round3d(const s5d_plan* p, int bt) {
     rows_written += std::min<int64_t>(C1, I1 - t * C1);
   }
   for (int64_t t = 0; t < nt2; ++t) {
-    const int64_t a = r + t * C2 - static_cast<int64_t>(bt) * r;
+    const int64_t a = r + t * C2 - LO2;
     cols_read += clip(a, a + B2, P2);
     cols_written += std::min<int64_t>(C2, I2 - t * C2);
   }
@@ -193,10 +198,12 @@ s5d_status model_plan(const s5d_plan* p, s5d_model* out) {
                .first;
     const RoundModel& m = it->second;
     const double ta = m.ops / rt.valu, tg = m.gm / rt.hbm, tl = m.lds / rt.lds;
-    // workgroup-slot efficiency: the launch runs in ceil(wgs / slots) waves
-    // of slots; the last one is partly empty
+    // slot efficiency: with fewer workgroups than resident slots the machine
+    // is part idle; otherwise the last workgroups finish unevenly, a tail of
+    // about kTail workgroup durations (one workgroup lasts body * slots / wgs)
     const double slots = static_cast<double>(rt.cus) * m.wg_per_cu;
-    const double fill = static_cast<double>(m.wgs) / (std::ceil(static_cast<double>(m.wgs) / slots) * slots);
+    const double frac = slots / static_cast<double>(std::max<int64_t>(m.wgs, 1));
+    const double fill = 1.0 / (std::max(1.0, frac) + kTail * std::min(1.0, frac));
     total += std::max(ta, std::max(tg, tl)) / fill;
     t_alu += ta;
     t_hbm += tg;

@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import stencil_inputs as si
+from geometry import compute_width
 from gpu_util import run_gpu, say
 from paper_2001_01473_amd import build as s5d_build
 
@@ -52,7 +53,7 @@ def _vid3(v):
 @pytest.mark.parametrize("v", V2, ids=[_vid2(v) for v in V2])
 def test_comp2d_variant_bitwise(v):
     dtype, box, r, cpl, bt, nr = v
-    C = 64 * cpl - 2 * bt * r
+    C = compute_width(64 * cpl, bt, r, 4)
     interior = (3 * (19 + bt) + 5, 2 * C + C // 2 + 7)
     T = 2 * bt + 1
     c32, g32 = _signed_case(700 + bt, 2, r, bool(box), interior, T)
@@ -64,7 +65,7 @@ def test_comp2d_variant_bitwise(v):
 @pytest.mark.parametrize("v", V3, ids=[_vid3(v) for v in V3])
 def test_comp3d_variant_bitwise(v):
     dtype, box, r, cpl, m, nw, bt, nr = v
-    C1, C2 = nw * m - 2 * bt * r, 64 * cpl - 2 * bt * r
+    C1, C2 = nw * m - 2 * bt * r, compute_width(64 * cpl, bt, r, 4)
     chunk = 7 + bt
     interior = (2 * chunk + 3, 2 * C1 + C1 // 2 + 3, C2 + C2 // 3 + 5)
     T = 2 * bt + 1

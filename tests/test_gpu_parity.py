@@ -16,6 +16,7 @@ import pytest
 import oracle
 import pins
 import stencil_inputs as si
+from geometry import compute_width
 from gpu_util import rel_errors, run_gpu, say
 from paper_2001_01473_amd import build as s5d_build
 
@@ -36,7 +37,7 @@ def _geometry(v):
     blocks plus a ragged tail; the stream block may be shorter than the
     warm-up (b_T * r rows)."""
     dtype, box, r, cpl, bt, nr = v
-    C = 64 * cpl - 2 * bt * r
+    C = compute_width(64 * cpl, bt, r, 4 if dtype == 0 else 8)
     I1 = 2 * C + C // 2 + 7
     chunk = 19 + bt
     I0 = 3 * chunk + 5

@@ -12,6 +12,7 @@ import pytest
 import oracle
 import pins
 import stencil_inputs as si
+from geometry import compute_width
 from gpu_util import rel_errors, run_gpu, say
 from paper_2001_01473_amd import build as s5d_build
 
@@ -31,7 +32,7 @@ def _vid(v):
 def _geometry(v):
     dtype, box, r, cpl, m, nw, bt, nr = v
     C1 = nw * m - 2 * bt * r
-    C2 = 64 * cpl - 2 * bt * r
+    C2 = compute_width(64 * cpl, bt, r, 4 if dtype != 1 else 8)
     I1 = 2 * C1 + C1 // 2 + 3
     I2 = C2 + C2 // 3 + 5
     chunk = 7 + bt
