@@ -146,8 +146,9 @@ s5d_status s5d_run(const s5d_plan *plan, void *buf0, void *buf1, void *stream,
  * The model follows AN5D's "Performance Model": per launch, count the vector
  * ALU work, the HBM traffic and the LDS traffic of every wave (all lanes
  * compute every fused level; lanes outside the grid move no data; LDS carries
- * the 3D edge-row exchange), divide each by the device's rate (VALU 64
- * lane-operations per clock per CU, HBM 6.0e12 B/s sustained, LDS 128 B per
+ * the 3D edge-row exchange), divide each by the device's rate (VALU 128
+ * float32 or 64 float64 lane-operations per clock per CU, HBM 6.0e12 B/s
+ * sustained, LDS 128 B per
  * clock per CU), take the largest and divide by the slot efficiency
  * 1 / (max(1, s/g) + 0.75 min(1, s/g)) for g workgroups and s resident slots
  * (an idle part of the machine when g < s, else a tail of about 0.75

@@ -35,14 +35,133 @@ struct DirectArgs {
   int32_t n0, n1, n2;  // tiles along each axis (2D: n2 = 1)
 };
 
+// Box stencils: each thread owns XB consecutive cells along the last axis in
+// NPR (plane, row) pairs.  Row by row in canonical order it reads the XB + 2r
+// staged values the row contributes once and feeds all 2r+1 terms of its XB
+// cells from registers (each cell still sums in (d0, d1, d2) order), so LDS
+// reads per term fall from 1 to (XB + 2r) / (XB (2r+1)).
+template <typename T, int ACC, int NDIM, int R>
+__device__ __forceinline__ void direct_box_cells(const DirectArgs& a, const T* tile, const T* __restrict__ c,
+                                                 T* __restrict__ dst, int oz, int oy, int ox, int PZ, int PY,
+                                                 int PX) {
+  (void)a;
+  constexpr int DX = direct_dx<NDIM, R>();
+  constexpr int DY = NDIM == 2 ? kDirectY2 : kDirectY3;
+  constexpr int DZ = NDIM == 2 ? 1 : kDirectZ3;
+  constexpr int SX = DX + 2 * R, SY = DY + 2 * R;
+  constexpr int XB = 4;
+  constexpr int TXN = DX / XB;        // threads along the last axis
+  constexpr int TYN = 256 / TXN;      // threads over the (plane, row) pairs
+  constexpr int NPR = DZ * DY / TYN;  // (plane, row) pairs per thread
+  static_assert(DX % XB == 0 && (DZ * DY) % TYN == 0 && NPR >= 1, "direct tile does not split evenly");
+  constexpr int E = 2 * R + 1;
+  const int tx = threadIdx.x % TXN, tyz = threadIdx.x / TXN;
+  Accum<T, ACC> acc[NPR][XB];
+  constexpr int NROWS = NDIM == 3 ? E * E : E;
+  // rows one at a time (a runtime loop keeps one segment per pair live); the
+  // first term of every cell is the first column of row 0
+#pragma unroll 1
+  for (int row = 0; row < NROWS; ++row) {
+    const int D0 = NDIM == 3 ? row / E : 0, D1 = NDIM == 3 ? row % E : row;
+    const T* __restrict__ crow = c + row * E;
+    sfor<NPR>([&](auto P) S5D_INL {
+      const int pr = tyz + TYN * P;
+      const int z = NDIM == 3 ? pr / DY : 0, y = NDIM == 3 ? pr % DY : pr;
+      const int base = NDIM == 3 ? ((z + D0) * SY + y + D1) * SX + XB * tx : (y + D1) * SX + XB * tx;
+      T seg[XB + 2 * R];
+      sfor<XB + 2 * R>([&](auto X) S5D_INL { seg[X] = tile[base + X]; });
+      sfor<E>([&](auto D2) S5D_INL {
+        const T ck = crow[D2];
+        sfor<XB>([&](auto J) S5D_INL {
+          if (D2 == 0 && row == 0)
+            acc[P][J].first(ck, seg[J + D2]);
+          else
+            acc[P][J].add(ck, seg[J + D2]);
+        });
+      });
+    });
+  }
+#pragma unroll
+  for (int P = 0; P < NPR; ++P) {
+    const int pr = tyz + TYN * P;
+    const int z = NDIM == 3 ? pr / DY : 0, y = NDIM == 3 ? pr % DY : pr;
+    const int gz = oz + R + z, gy = oy + R + y;
+    const bool row_in = gy < PY - R && (NDIM == 2 || gz < PZ - R);
+#pragma unroll
+    for (int J = 0; J < XB; ++J) {
+      const int gx = ox + R + XB * tx + J;
+      if (row_in && gx < PX - R)
+        dst[(static_cast<int64_t>(NDIM == 3 ? gz : 0) * PY + gy) * PX + gx] = acc[P][J].value();
+    }
+  }
+}
+
+// Star stencils (few terms, mostly one per row): one column per thread, RY
+// rows per plane; consecutive threads read consecutive LDS words.
+template <typename T, int ACC, int NDIM, int R>
+__device__ __forceinline__ void direct_star_cells(const DirectArgs& a, const T* tile, const T* __restrict__ c,
+                                                  T* __restrict__ dst, int oz, int oy, int ox, int PZ, int PY,
+                                                  int PX) {
+  (void)a;
+  constexpr int DX = direct_dx<NDIM, R>();
+  constexpr int DY = NDIM == 2 ? kDirectY2 : kDirectY3;
+  constexpr int DZ = NDIM == 2 ? 1 : kDirectZ3;
+  constexpr int SX = DX + 2 * R, SY = DY + 2 * R;
+  constexpr int TY = 256 / DX;  // threads stacked along the rows
+  constexpr int RY = DY / TY;   // rows (per plane) per thread
+  const int tx = threadIdx.x % DX, ty = threadIdx.x / DX;
+  Accum<T, ACC> acc[DZ][RY];
+  // cell (z, j) of this thread: tile plane z + R, row ty + TY j + R, column tx + R
+  auto at = [&](int z, int j, int d0, int d1, int d2) S5D_INL -> T {
+    if constexpr (NDIM == 3)
+      return tile[((z + R + d0) * SY + ty + TY * j + R + d1) * SX + tx + R + d2];
+    else
+      return tile[(ty + TY * j + R + d0) * SX + tx + R + d1];
+  };
+  int k = 0;
+  bool first = true;
+  auto term = [&](int d0, int d1, int d2) S5D_INL {
+    const T ck = c[k++];
+#pragma unroll
+    for (int z = 0; z < DZ; ++z)
+#pragma unroll
+      for (int j = 0; j < RY; ++j) {
+        if (first)
+          acc[z][j].first(ck, at(z, j, d0, d1, d2));
+        else
+          acc[z][j].add(ck, at(z, j, d0, d1, d2));
+      }
+    first = false;
+  };
+  // canonical order of the star's offsets
+  if constexpr (NDIM == 3) {
+    for (int d = -R; d < 0; ++d) term(d, 0, 0);
+    for (int d = -R; d < 0; ++d) term(0, d, 0);
+    for (int d = -R; d <= R; ++d) term(0, 0, d);
+    for (int d = 1; d <= R; ++d) term(0, d, 0);
+    for (int d = 1; d <= R; ++d) term(d, 0, 0);
+  } else {
+    for (int d = -R; d < 0; ++d) term(d, 0, 0);
+    for (int d = -R; d <= R; ++d) term(0, d, 0);
+    for (int d = 1; d <= R; ++d) term(d, 0, 0);
+  }
+  const int gx = ox + R + tx;
+#pragma unroll
+  for (int z = 0; z < DZ; ++z)
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      const int gz = oz + R + z, gy = oy + R + ty + TY * j;
+      const bool in = gx < PX - R && gy < PY - R && (NDIM == 2 || gz < PZ - R);
+      if (in) dst[(static_cast<int64_t>(NDIM == 3 ? gz : 0) * PY + gy) * PX + gx] = acc[z][j].value();
+    }
+}
+
 template <typename T, int ACC, int NDIM, int R, bool BOX>
 __device__ __forceinline__ void direct_block(const DirectArgs& a, int lb, T* tile) {
   constexpr int DX = direct_dx<NDIM, R>();
   constexpr int DY = NDIM == 2 ? kDirectY2 : kDirectY3;
   constexpr int DZ = NDIM == 2 ? 1 : kDirectZ3;
   constexpr int SX = DX + 2 * R, SY = DY + 2 * R, SZ = NDIM == 2 ? 1 : DZ + 2 * R;
-  constexpr int TY = 256 / DX;  // threads stacked along the rows
-  constexpr int RY = DY / TY;   // rows (per plane) per thread
   static_assert(SX * SY * SZ * sizeof(T) <= 65536, "staged tile exceeds 64 KiB");
   const T* __restrict__ src = static_cast<const T*>(a.src);
   T* __restrict__ dst = static_cast<T*>(a.dst);
@@ -68,60 +187,10 @@ __device__ __forceinline__ void direct_block(const DirectArgs& a, int lb, T* til
   }
   __syncthreads();
 
-  const int tx = threadIdx.x % DX, ty = threadIdx.x / DX;
-  Accum<T, ACC> acc[DZ][RY];
-  // cell (z, j) of this thread: tile plane z + R, row ty + TY j + R, column tx + R
-  auto at = [&](int z, int j, int d0, int d1, int d2) S5D_INL -> T {
-    if constexpr (NDIM == 3)
-      return tile[((z + R + d0) * SY + ty + TY * j + R + d1) * SX + tx + R + d2];
-    else
-      return tile[(ty + TY * j + R + d0) * SX + tx + R + d1];
-  };
-  int k = 0;
-  bool first = true;
-  auto term = [&](int d0, int d1, int d2) S5D_INL {
-    const T ck = c[k++];
-#pragma unroll
-    for (int z = 0; z < DZ; ++z)
-#pragma unroll
-      for (int j = 0; j < RY; ++j) {
-        if (first)
-          acc[z][j].first(ck, at(z, j, d0, d1, d2));
-        else
-          acc[z][j].add(ck, at(z, j, d0, d1, d2));
-      }
-    first = false;
-  };
-  if constexpr (BOX) {
-    for (int d0 = -R; d0 <= R; ++d0)
-      for (int d1 = -R; d1 <= R; ++d1) {
-        if constexpr (NDIM == 3) {
-          for (int d2 = -R; d2 <= R; ++d2) term(d0, d1, d2);
-        } else {
-          term(d0, d1, 0);
-        }
-      }
-  } else if constexpr (NDIM == 3) {
-    for (int d = -R; d < 0; ++d) term(d, 0, 0);
-    for (int d = -R; d < 0; ++d) term(0, d, 0);
-    for (int d = -R; d <= R; ++d) term(0, 0, d);
-    for (int d = 1; d <= R; ++d) term(0, d, 0);
-    for (int d = 1; d <= R; ++d) term(d, 0, 0);
-  } else {
-    for (int d = -R; d < 0; ++d) term(d, 0, 0);
-    for (int d = -R; d <= R; ++d) term(0, d, 0);
-    for (int d = 1; d <= R; ++d) term(d, 0, 0);
-  }
-
-  const int gx = ox + R + tx;
-#pragma unroll
-  for (int z = 0; z < DZ; ++z)
-#pragma unroll
-    for (int j = 0; j < RY; ++j) {
-      const int gz = oz + R + z, gy = oy + R + ty + TY * j;
-      const bool in = gx < PX - R && gy < PY - R && (NDIM == 2 || gz < PZ - R);
-      if (in) dst[(static_cast<int64_t>(NDIM == 3 ? gz : 0) * PY + gy) * PX + gx] = acc[z][j].value();
-    }
+  if constexpr (BOX)
+    direct_box_cells<T, ACC, NDIM, R>(a, tile, c, dst, oz, oy, ox, PZ, PY, PX);
+  else
+    direct_star_cells<T, ACC, NDIM, R>(a, tile, c, dst, oz, oy, ox, PZ, PY, PX);
 }
 
 template <typename T, int ACC, int NDIM, int R, bool BOX>

@@ -64,6 +64,10 @@ __device__ __forceinline__ double lane_from_upper(double v) {
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Cache policy of the kernels' stores (the buffer instructions' aux operand;
+// 0 = default).
+constexpr int kStoreAux = 0;
+
 // Buffer descriptors (gfx9 family: 3rd dword 0x00020000, raw byte
 // addressing).  An access whose byte offset is >= nbytes reads 0 / is dropped.
 constexpr uint32_t kOutOfRange = 0x80000000u;
@@ -78,11 +82,11 @@ __device__ __forceinline__ void buf_load(double& v, __amdgpu_buffer_rsrc_t rs, u
   v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, static_cast<int>(off), 0, 0));
 }
 __device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
-  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, static_cast<int>(off), 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, static_cast<int>(off), 0, kStoreAux);
 }
 __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
   using u2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(rs, 0, 0, 0));
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, static_cast<int>(off), 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, static_cast<int>(off), 0, kStoreAux);
 }
 // A lane's CPL consecutive cells as the widest stores that tile them (16, 8
 // or 4 bytes); an out-of-range offset drops the whole vector.
@@ -99,12 +103,12 @@ __device__ __forceinline__ void buf_store_lane(const T (&v)[CPL], __amdgpu_buffe
     const uint32_t o = off == kOutOfRange ? kOutOfRange : off + q * static_cast<uint32_t>(PIECE);
     if constexpr (PIECE == 16) {
       using u4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(rs, 0, 0, 0));
-      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, piece), rs, static_cast<int>(o), 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, piece), rs, static_cast<int>(o), 0, kStoreAux);
     } else if constexpr (PIECE == 8) {
       using u2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(rs, 0, 0, 0));
-      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, piece), rs, static_cast<int>(o), 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, piece), rs, static_cast<int>(o), 0, kStoreAux);
     } else {
-      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, piece), rs, static_cast<int>(o), 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, piece), rs, static_cast<int>(o), 0, kStoreAux);
     }
   }
 }

@@ -27,17 +27,18 @@
 namespace s5d {
 namespace {
 
-// Device rates.  VALU: 64 lane-operations per clock per CU (4 SIMDs of 16
-// lanes; packed float32 math is not used).  HBM: the practical streaming rate
-// of MI355X (a plain device copy sustains about 6 TB/s of the 8 TB/s peak).
-// LDS: 128 bytes per clock per CU.
+// Device rates.  VALU lane-operations per clock per CU: 128 in float32, 64
+// in float64 (MI355X's published vector peaks, 157.3 and 78.6 TFLOP/s, at 256
+// CUs and 2.4 GHz; the float32 rate is reached by unpacked operations too).
+// HBM: the practical streaming rate (a plain device copy sustains about
+// 6 TB/s of the 8 TB/s peak).  LDS: 128 bytes per clock per CU.
 struct Rates {
-  double valu, hbm, lds;
+  double valu, hbm, lds;  // valu: float32 lane-operations per second
   int cus;
 };
 
 Rates device_rates() {
-  Rates r{256 * 64 * 2.4e9, 6.0e12, 256 * 128 * 2.4e9, 256};
+  Rates r{256 * 128 * 2.4e9, 6.0e12, 256 * 128 * 2.4e9, 256};
   int dev = 0, cus = 0, khz = 0;
   if (hipGetDevice(&dev) == hipSuccess &&
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
@@ -45,7 +46,7 @@ Rates device_rates() {
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeClockRate, dev) == hipSuccess && khz > 0)
       clock = khz * 1e3;
     r.cus = cus;
-    r.valu = cus * 64.0 * clock;
+    r.valu = cus * 128.0 * clock;
     r.lds = cus * 128.0 * clock;
   }
   (void)hipGetLastError();
@@ -197,7 +198,8 @@ s5d_status model_plan(const s5d_plan* p, s5d_model* out) {
                                       : (p->d.ndim == 3 ? model_round3d(p, bt) : model_round2d(p, bt)))
                .first;
     const RoundModel& m = it->second;
-    const double ta = m.ops / rt.valu, tg = m.gm / rt.hbm, tl = m.lds / rt.lds;
+    const double valu = p->elem == 8 ? rt.valu / 2 : rt.valu;  // float64 at half rate
+    const double ta = m.ops / valu, tg = m.gm / rt.hbm, tl = m.lds / rt.lds;
     // slot efficiency: with fewer workgroups than resident slots the machine
     // is part idle; otherwise the last workgroups finish unevenly, a tail of
     // about kTail workgroup durations (one workgroup lasts body * slots / wgs)

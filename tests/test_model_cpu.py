@@ -20,7 +20,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(_lib.LIB_PATH),
                                 reason="libstencil5d.so not built")
 
 HBM = 6.0e12
-VALU = 256 * 64 * 2.4e9
+VALU = {4: 256 * 128 * 2.4e9, 8: 256 * 64 * 2.4e9}  # lane-operations/s by element size
 
 
 def _plan(ndim, r, box, dtype, interior, steps, accum=0, **tuning):
@@ -66,7 +66,7 @@ def test_model2d_counts_match_brute_force(I, r, box, dtype, bt, cpl, h):
     ops = n + (2 * r + 1 if box else 1) * 2 * r * (w // 4) / cpl + 0.5
     assert m["valu_ops"] == pytest.approx(2 * comp * ops, rel=1e-12)
     assert m["t_hbm"] == pytest.approx(2 * nbytes / HBM, rel=1e-9)
-    assert m["t_alu"] == pytest.approx(2 * comp * ops / VALU, rel=1e-9)
+    assert m["t_alu"] == pytest.approx(2 * comp * ops / VALU[w], rel=1e-9)
     # the slot efficiency divides the larger of the two terms
     slots = 256 * 2  # occupancy is unknown without a device: two workgroups per CU
     frac = slots / wgs
