@@ -147,3 +147,21 @@ def test_many_grid_workload_bitwise_and_oracle():
         n = len(c)
         bound = s["steps"] * (pins.gamma(n, pins.U32) + pins.U32) * float(g.max()) * 1.01
         assert float(np.max(np.abs(outs[0][i].astype(np.float64) - ref))) <= bound, i
+
+
+def test_autotuned_plan_same_bits():
+    """The autotuner's choice (cached, then taken by a plan without tuning)
+    gives the same bits as the library's default choice."""
+    s5d.tune_cache_clear()
+    spec = dict(ndim=2, radius=1, box=False, interior=(900, 1400), steps=37, seed=si.item_seed(9, 1))
+    p0, g, _ = _plan(spec, np.float32)
+    base = _alone(p0, g)
+    case = si.make_case(spec["seed"], 2, 1, False, spec["interior"], spec["steps"])
+    tun, rep = s5d.autotune(ndim=2, radius=1, box=False, dtype="f32", interior=spec["interior"],
+                            steps=spec["steps"], coeffs=case.coeffs, top_k=3)
+    assert rep["n_measured"] == 3 and rep["best_seconds_per_step"] > 0
+    p1, _, _ = _plan(spec, np.float32)
+    got = p1.query()
+    assert (got["bt"], got["stream_chunk"]) == (min(tun["bt"], spec["steps"]), tun["stream_chunk"])
+    np.testing.assert_array_equal(_alone(p1, g), base)
+    s5d.tune_cache_clear()
