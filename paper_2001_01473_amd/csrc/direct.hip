@@ -1,20 +1,34 @@
-// Instantiations of the direct kernels: every kernel kind, radius 1..4 and
-// shape, in 2D and 3D.
+// Instantiations of the direct (one step per launch) kernels: every kernel
+// kind, radius 1..4 and shape, in 2D and 3D.
 #include "direct.h"
+#include "stream2d.h"
 
 namespace s5d {
 namespace {
 
+// 2D: the row-streaming kernel (stream2d.h), except for box stencils of
+// radius 3 and 4, whose 2r+1 full-row reads per thread lose to the LDS-staged
+// tiles (measured on MI355X); 3D: the LDS-staged tiles.
 template <typename T, int ACC, int R, bool BOX>
 Kernel2D make2d() {
-  return Kernel2D{&launch_direct2d<T, ACC, R, BOX>,
-                  &occupancy_direct<T, ACC, 2, R, BOX>,
-                  0,
-                  1,
-                  direct_dx<2, R>(),
-                  &fill_direct2d<R>,
-                  &launch_direct_batch<T, ACC, 2, R, BOX>,
-                  static_cast<int>(sizeof(DirectArgs))};
+  if constexpr (BOX && R >= 3)
+    return Kernel2D{&launch_direct2d<T, ACC, R, BOX>,
+                    &occupancy_direct<T, ACC, 2, R, BOX>,
+                    0,
+                    1,
+                    direct_dx<2, R>(),
+                    &fill_direct2d<R>,
+                    &launch_direct_batch<T, ACC, 2, R, BOX>,
+                    static_cast<int>(sizeof(DirectArgs))};
+  else
+    return Kernel2D{&launch_stream2d<T, ACC, R, BOX>,
+                    &occupancy_stream2d<T, ACC, R, BOX>,
+                    0,
+                    1,
+                    256 * stream2d_cpl<T>(),
+                    &fill_stream2d<T>,
+                    &launch_stream2d_batch<T, ACC, R, BOX>,
+                    static_cast<int>(sizeof(Stream2DArgs))};
 }
 
 template <typename T, int ACC, int R, bool BOX>

@@ -1,0 +1,169 @@
+// Direct 2D kernel: one time step per launch, streaming whole rows.
+//
+// Workgroup (row p, segment s) computes the cells of interior row p in
+// columns [R + s*SEG, R + (s+1)*SEG), SEG = 256 threads x CPL cells.  Each
+// thread reads its CPL cells and the r cells on either side from the 2r+1
+// rows p-r .. p+r straight from global memory and sums every cell's terms in
+// the canonical (d0, d1) order, with the same accumulation policy as the
+// blocked kernels -- so both give the same bits.  Consecutive workgroups of an
+// XCD take consecutive segments and rows, so the rows a workgroup shares with
+// its neighbours are still in that XCD's L2: HBM sees about one read and one
+// write per cell, in address order, like a plain streaming copy.  No LDS, no
+// barrier.
+#pragma once
+
+#include "kcommon.h"
+
+namespace s5d {
+
+struct Stream2DArgs {
+  const void* src;
+  void* dst;
+  const void* coef;  // device array of the coefficients, canonical order, working type
+  int32_t I0, I1;
+  int32_t nseg;      // segments per row
+  int32_t pad;
+};
+
+template <typename T>
+constexpr int stream2d_cpl() {
+  return 16 / static_cast<int>(sizeof(T));  // one 16-byte vector per thread
+}
+
+template <typename T, int ACC, int R, bool BOX>
+__device__ __forceinline__ void stream2d_block(const Stream2DArgs& a, int lb) {
+  constexpr int CPL = stream2d_cpl<T>();
+  constexpr int SEG = 256 * CPL;
+  constexpr int E = 2 * R + 1;
+  const int P1 = a.I1 + 2 * R;
+  const int p = R + lb / a.nseg;            // interior row
+  const int seg = lb - (lb / a.nseg) * a.nseg;
+  const int c0 = R + seg * SEG + static_cast<int>(threadIdx.x) * CPL;  // first column of this thread
+  const T* __restrict__ src = static_cast<const T*>(a.src);
+  T* __restrict__ dst = static_cast<T*>(a.dst);
+  const T* __restrict__ c = static_cast<const T*>(a.coef);
+  // the thread's cells and their r neighbours on each side, per stencil row;
+  // columns beyond the padded row read 0 (they feed no stored cell)
+  auto load_row = [&](T (&x)[CPL + 2 * R], int row, bool full) S5D_INL {
+    const T* rp = src + static_cast<int64_t>(row) * P1;
+    if (c0 + CPL + R <= P1) {
+      const LaneVec<T, CPL> v = *reinterpret_cast<const LaneVec<T, CPL>*>(rp + c0);
+      sfor<CPL>([&](auto K) S5D_INL { x[R + K] = v.v[K]; });
+      if (full)
+        sfor<R>([&](auto J) S5D_INL {
+          x[J] = rp[c0 - R + J];
+          x[R + CPL + J] = rp[c0 + CPL + J];
+        });
+    } else {
+      sfor<CPL + 2 * R>([&](auto X) S5D_INL {
+        const int col = c0 - R + X;
+        x[X] = (col < P1 && (full || (X >= R && X < R + CPL))) ? rp[col] : T(0);
+      });
+    }
+  };
+  Accum<T, ACC> acc[CPL];
+  sfor<E>([&](auto D0) S5D_INL {
+    constexpr int d0 = decltype(D0)::value - R;
+    constexpr bool full = BOX || d0 == 0;  // rows that need in-row neighbours
+    T x[CPL + 2 * R];
+    load_row(x, p + d0, full);
+    if constexpr (BOX) {
+      sfor<E>([&](auto D1) S5D_INL {
+        const T ck = c[decltype(D0)::value * E + decltype(D1)::value];
+        sfor<CPL>([&](auto K) S5D_INL {
+          if constexpr (decltype(D0)::value == 0 && decltype(D1)::value == 0)
+            acc[K].first(ck, x[K + D1]);
+          else
+            acc[K].add(ck, x[K + D1]);
+        });
+      });
+    } else if constexpr (d0 != 0) {
+      const T ck = c[d0 < 0 ? d0 + R : 3 * R + d0];
+      sfor<CPL>([&](auto K) S5D_INL {
+        if constexpr (d0 == -R)
+          acc[K].first(ck, x[R + K]);
+        else
+          acc[K].add(ck, x[R + K]);
+      });
+    } else {
+      sfor<E>([&](auto D1) S5D_INL {
+        const T ck = c[R + decltype(D1)::value];
+        sfor<CPL>([&](auto K) S5D_INL { acc[K].add(ck, x[K + D1]); });
+      });
+    }
+  });
+  T out[CPL];
+  sfor<CPL>([&](auto K) S5D_INL { out[K] = acc[K].value(); });
+  T* wp = dst + static_cast<int64_t>(p) * P1;
+  if (c0 + CPL <= a.I1 + R) {
+    LaneVec<T, CPL> v;
+    sfor<CPL>([&](auto K) S5D_INL { v.v[K] = out[K]; });
+    *reinterpret_cast<LaneVec<T, CPL>*>(wp + c0) = v;
+  } else {
+    sfor<CPL>([&](auto K) S5D_INL {
+      if (c0 + K < a.I1 + R) wp[c0 + K] = out[K];
+    });
+  }
+}
+
+template <typename T, int ACC, int R, bool BOX>
+__global__ __launch_bounds__(256) void stream2d_kernel(Stream2DArgs a) {
+  stream2d_block<T, ACC, R, BOX>(a, xcd_logical_block(blockIdx.x, gridDim.x));
+}
+
+template <typename T, int ACC, int R, bool BOX>
+__global__ __launch_bounds__(256) void stream2d_batch_kernel(const Stream2DArgs* __restrict__ items,
+                                                             const BlockMap* __restrict__ map) {
+  const BlockMap m = map[xcd_logical_block(blockIdx.x, gridDim.x)];
+  const Stream2DArgs a = items[__builtin_amdgcn_readfirstlane(m.item)];
+  stream2d_block<T, ACC, R, BOX>(a, __builtin_amdgcn_readfirstlane(m.block));
+}
+
+template <typename T>
+int64_t stream2d_args(Stream2DArgs& a, const Round2D& rd) {
+  constexpr int SEG = 256 * stream2d_cpl<T>();
+  a.src = rd.src;
+  a.dst = rd.dst;
+  a.coef = rd.dcoef;
+  a.I0 = rd.I0;
+  a.I1 = rd.I1;
+  a.nseg = (rd.I1 + SEG - 1) / SEG;
+  a.pad = 0;
+  const int64_t nblk = static_cast<int64_t>(rd.I0) * a.nseg;
+  return nblk > INT32_MAX ? 0 : nblk;
+}
+
+template <typename T, int ACC, int R, bool BOX>
+hipError_t launch_stream2d(const Round2D& rd) {
+  Stream2DArgs a;
+  const int64_t nblk = stream2d_args<T>(a, rd);
+  if (nblk == 0) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((stream2d_kernel<T, ACC, R, BOX>), dim3(static_cast<unsigned>(nblk)), dim3(256), 0, rd.stream,
+                     a);
+  return hipGetLastError();
+}
+
+template <typename T>
+int fill_stream2d(void* item, const Round2D& rd) {
+  Stream2DArgs a;
+  const int64_t nblk = stream2d_args<T>(a, rd);
+  __builtin_memcpy(item, &a, sizeof(a));
+  return static_cast<int>(nblk);
+}
+
+template <typename T, int ACC, int R, bool BOX>
+hipError_t launch_stream2d_batch(const void* items, const BlockMap* map, int nblocks, hipStream_t stream) {
+  hipLaunchKernelGGL((stream2d_batch_kernel<T, ACC, R, BOX>), dim3(nblocks), dim3(256), 0, stream,
+                     static_cast<const Stream2DArgs*>(items), map);
+  return hipGetLastError();
+}
+
+template <typename T, int ACC, int R, bool BOX>
+int occupancy_stream2d() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stream2d_kernel<T, ACC, R, BOX>, 256, 0) != hipSuccess)
+    return 0;
+  return nb;
+}
+
+}  // namespace s5d

@@ -119,8 +119,11 @@ RoundModel model_round_direct(const s5d_plan* p) {
   const int64_t w = p->elem;
   double cells = 1, staged = 1;
   int64_t tiles = 1;
-  // tile shape of the direct kernels: 2D 16 x 64, 3D 4 x 8 x (64, or 32 for r >= 3)
-  const int dims2[2] = {16, 64};
+  // 2D: one row of 256 x (16 bytes / w) cells per workgroup, no LDS (box
+  // radius 3-4: LDS tiles of 16 x 64); 3D: LDS tiles of 4 x 8 x (64, or 32
+  // for r >= 3) cells
+  const bool lds2 = p->d.shape == S5D_BOX && r >= 3;
+  const int dims2[2] = {lds2 ? 16 : 1, lds2 ? 64 : 256 * 16 / static_cast<int>(w)};
   const int dims3[3] = {4, 8, r >= 3 ? 32 : 64};
   for (int a = 0; a < nd; ++a) {
     const int64_t I = p->d.interior[a];
@@ -133,8 +136,9 @@ RoundModel model_round_direct(const s5d_plan* p) {
   const double n_terms = static_cast<double>(p->coeffs.size());
   m.gm = 2.0 * cells * w;
   const double ops_term = p->kind == KIND_F32_COMP ? 9.0 : 1.0;
-  m.ops = cells * (n_terms * ops_term + 2.0) + static_cast<double>(tiles) * staged * 2.0;
-  m.lds = cells * n_terms * w + static_cast<double>(tiles) * staged * w;
+  const bool uses_lds = nd == 3 || lds2;
+  m.ops = cells * (n_terms * ops_term + 2.0) + (uses_lds ? static_cast<double>(tiles) * staged * 2.0 : 0.0);
+  m.lds = uses_lds ? cells * n_terms * w + static_cast<double>(tiles) * staged * w : 0.0;
   m.wgs = tiles;
   const Kernel2D& k2 = p->by_bt[1];
   const Kernel3D& k3 = p->by_bt3[1];
