@@ -467,6 +467,69 @@ def bench_serve(n_requests=32, loads=(0.8,), budgets=(64 << 30,)):
     return out
 
 
+def bench_accuracy():
+    """Error after T steps of float32 (plain and compensated accumulation)
+    against float64, all three started from the same float32-rounded grid and
+    coefficients and run on the GPU; the norms are the library's float64
+    reductions.  The float64 result is tied to the CPU oracle on sampled 2D
+    cells (the oracle run on the window of the initial grid that a cell's T-step
+    result depends on).  Workloads: 512^3 star3d1r and box3d1r, 16384^2
+    star2d1r, T = 1000."""
+    import torch
+    import oracle
+    import paper_2001_01473_amd as s5d
+    out = []
+    for ndim, r, box, interior in ((3, 1, False, (N3, N3, N3)), (3, 1, True, (N3, N3, N3)),
+                                   (2, 1, False, (N, N))):
+        rng = np.random.default_rng(si.workload_seed(2 if ndim == 3 else 1))
+        c32 = si.random_coeffs(rng, si.n_points(ndim, r, box)).astype(np.float32)
+        c = c32.astype(np.float64)
+        shape = si.padded_shape(interior, r)
+        g32 = _device_grid(shape, "f32", si.workload_seed(5))
+        results = {}
+        for kind, dt, accum in (("f64", torch.float64, "plain"), ("f32", torch.float32, "plain"),
+                                ("f32c", torch.float32, "compensated")):
+            x = g32.to(dt, copy=True)  # each run starts from its own copy of the grid
+            y = torch.empty_like(x)
+            p = s5d.Plan(ndim=ndim, radius=r, box=box, dtype="f64" if kind == "f64" else "f32",
+                         interior=interior, steps=T_STEPS, coeffs=c, accum=accum)
+            idx = p.run(x, y)
+            torch.cuda.synchronize()
+            p.close()
+            results[kind] = x if idx == 0 else y
+            del x, y
+        assert not any(v.data_ptr() == g32.data_ptr() for v in results.values())
+        ref = results["f64"]
+        rec = {"stencil": stencil_name(r, box).replace("2d", "%dd" % ndim),
+               "interior": list(interior), "steps": T_STEPS}
+        for kind in ("f32", "f32c"):
+            nm = s5d.error_norms(results[kind], ref).cpu().numpy()
+            rec[kind] = {"max_abs_err": float(nm[0]), "max_rel_err": float(nm[2]),
+                         "rms_err": float(nm[3]), "normwise": float(nm[0] / nm[1])}
+        rec["f64_vs_oracle_sampled_rel"] = None
+        if ndim == 2:
+            g_host = g32.cpu().numpy().astype(np.float64)
+            prng = np.random.default_rng(7)
+            H = T_STEPS * r + r
+            worst = 0.0
+            for _ in range(3):
+                pt = tuple(int(v) for v in prng.integers(r, np.array(shape) - r))
+                lo = [max(0, pt[a] - H) for a in range(ndim)]
+                hi = [min(shape[a], pt[a] + H + 1) for a in range(ndim)]
+                win = g_host[tuple(slice(lo[a], hi[a]) for a in range(ndim))]
+                want = oracle.sweep(win, radius=r, box=box, coeffs=c, steps=T_STEPS)[
+                    tuple(pt[a] - lo[a] for a in range(ndim))]
+                worst = max(worst, abs(float(ref[pt].item()) - want) / abs(want))
+            rec["f64_vs_oracle_sampled_rel"] = worst
+        out.append(rec)
+        print("accuracy %s: f32 normwise %.3g, compensated %.3g" % (
+            rec["stencil"], rec["f32"]["normwise"], rec["f32c"]["normwise"]), file=sys.stderr,
+            flush=True)
+        del results, ref, g32
+        torch.cuda.empty_cache()
+    return out
+
+
 def ingest_counters(fetch_dir, write_dir, out_json, out_md, command):
     """Per-launch HBM traffic of the headline kernel from two rocprofv3 --pmc
     runs of `bench.py --probe` (FETCH_SIZE, then WRITE_SIZE), each scaled by what
@@ -565,6 +628,8 @@ def main(argv=None):
     ap.add_argument("--batch", action="store_true",
                     help="also measure the 64-grid batched workload")
     ap.add_argument("--serve", action="store_true", help="also measure the serving loop")
+    ap.add_argument("--accuracy", action="store_true",
+                    help="also report float32 and compensated errors against float64 after T steps")
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-loads", default="0.8")
     ap.add_argument("--serve-budgets-gib", default="64")
@@ -599,6 +664,8 @@ def main(argv=None):
         return 0
 
     extras = {}
+    if args.accuracy:
+        extras["accuracy"] = bench_accuracy()
     if args.batch:
         extras["batched"] = bench_batch()
     if args.serve:
