@@ -92,7 +92,10 @@ typedef struct s5d_tuning {
     int32_t bt;             /* temporal blocking degree b_T: time steps fused per launch */
     int32_t tile0;          /* 2D: b_S along axis 1; 3D: b_S along axis 1 (rows) */
     int32_t tile1;          /* 3D: b_S along axis 2 (columns); 2D: unused */
-    int32_t stream_chunk;   /* h_SN: axis-0 length of one stream block */
+    int32_t stream_chunk;   /* h_SN: axis-0 length of one stream block (2D:
+                               each of 8 bands of ceil(I0/8) rows, one per
+                               XCD, ends in blocks of h_SN/2 rows when
+                               h_SN >= 32) */
     int32_t cells_per_lane; /* consecutive cells of the last axis owned by one lane */
     int32_t rows_per_wave;  /* 3D: consecutive axis-1 rows held by one wave */
     int32_t waves_per_eu;   /* reserved, 0 */
@@ -146,10 +149,10 @@ s5d_status s5d_run(const s5d_plan *plan, void *buf0, void *buf1, void *stream,
  * The model follows AN5D's "Performance Model": per launch, count the vector
  * ALU work, the HBM traffic and the LDS traffic of every wave (all lanes
  * compute every fused level; lanes outside the grid move no data; LDS carries
- * the 3D edge-row exchange), divide each by the device's rate (VALU 128
- * float32 or 64 float64 lane-operations per clock per CU, HBM 6.0e12 B/s
- * sustained, LDS 128 B per
- * clock per CU), take the largest and divide by the slot efficiency
+ * the 3D edge-row exchange), divide each by the device's rate (VALU 64
+ * lane-operations per clock per CU in float32 and float64 alike, as the
+ * kernels use no packed float32 instructions; HBM 6.0e12 B/s sustained, LDS
+ * 128 B per clock per CU), take the largest and divide by the slot efficiency
  * 1 / (max(1, s/g) + 0.75 min(1, s/g)) for g workgroups and s resident slots
  * (an idle part of the machine when g < s, else a tail of about 0.75
  * workgroup durations as the last ones finish unevenly).  The whole sweep is

@@ -286,9 +286,10 @@ s5d_status plan_2d(s5d_plan* p, const s5d_tuning& req, int box, int r) {
   }
   if (req.tile1 > 0 || req.rows_per_wave > 0) return fail(S5D_EINVAL, "tile1 and rows_per_wave are 3D fields");
   int bt = req.bt;
-  if (cpl == 0 && (bt == 0 || bt == default_bt(p->kind, box, r))) {
+  if (cpl == 0) {
+    // the default tile width, if it is built to the requested (or default) depth
     const int c = default_tuning(p->kind, box, r).cpl;
-    if (max_bt2d(p->kind, box, r, c) >= default_bt(p->kind, box, r)) cpl = c;
+    if (max_bt2d(p->kind, box, r, c) >= (bt > 0 ? bt : default_bt(p->kind, box, r))) cpl = c;
   }
   if (cpl == 0) {
     // widest tile that still reaches the requested (or default) depth

@@ -61,6 +61,57 @@ __device__ __forceinline__ double lane_from_upper(double v) {
   return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
+// The same shifts folded into the float32 product of a term (VOP2 DPP):
+// fma_dpp<true>(s, x, c) = fma(x of lane l-1, c, s), fma_dpp<false> takes lane
+// l+1; mul_dpp likewise returns x * c.  One instruction instead of a DPP move
+// plus the FMA, with the same bits (the product is commutative and exact in
+// the FMA).  A DPP read of a VGPR must come at least two wait states after the
+// VALU write of that VGPR; the compiler cannot see the DPP inside the asm, so
+// each carries its own s_nop 1.  c must be a VGPR (VOP2 src1).
+template <bool SHR>
+__device__ __forceinline__ float fma_dpp(float s, float x, float c) {
+  if constexpr (SHR)
+    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "+v"(s) : "v"(x), "v"(c));
+  else
+    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "+v"(s) : "v"(x), "v"(c));
+  return s;
+}
+template <bool SHR>
+__device__ __forceinline__ float mul_dpp(float x, float c) {
+  float p;
+  if constexpr (SHR)
+    asm("s_nop 1\n\tv_mul_f32_dpp %0, %1, %2 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "=v"(p) : "v"(x), "v"(c));
+  else
+    asm("s_nop 1\n\tv_mul_f32_dpp %0, %1, %2 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "=v"(p) : "v"(x), "v"(c));
+  return p;
+}
+// A wave-uniform float copied into a VGPR (an SGPR cannot be a VOP2 DPP
+// operand).
+__device__ __forceinline__ float to_vgpr(float c) {
+  float v;
+  asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(c));
+  return v;
+}
+
+// Copy of a wave-uniform struct in global memory, dword by dword through
+// readfirstlane, so that the compiler keeps every field in SGPRs: a plain
+// struct copy may be lowered to vector loads, after which buffer descriptors
+// built from its fields would need a waterfall loop per access.
+template <typename S>
+__device__ __forceinline__ S uniform_copy(const S& src) {
+  static_assert(sizeof(S) % 4 == 0, "dword-sized structs only");
+  S out;
+  const int* p = reinterpret_cast<const int*>(&src);
+  int* q = reinterpret_cast<int*>(&out);
+#pragma unroll
+  for (int i = 0; i < static_cast<int>(sizeof(S) / 4); ++i) q[i] = __builtin_amdgcn_readfirstlane(p[i]);
+  return out;
+}
+
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 

@@ -51,14 +51,56 @@ struct Round2D {
   hipStream_t stream;
 };
 
+// Stream blocks of a 2D launch, laid out for the XCDs.  Workgroups are
+// dispatched round-robin over the kXcds XCDs, so workgroup b runs on XCD
+// b % kXcds; that XCD takes band b % kXcds of the rows (hb = ceil(I0 / kXcds)
+// rows) and walks its workgroups in the order b / kXcds.  A band is cut into
+// n1 blocks of h1 rows followed by n2 blocks of h2 rows (h2 = h1 / 2 when
+// h1 >= 32, the last block possibly shorter): each XCD runs its long blocks
+// first and ends on short ones, which shortens the tail of the launch, and
+// neighbouring tiles of a block row run on one XCD and share its L2.
+constexpr int kXcds = 8;
+
+struct Bands2D {
+  int32_t hb;      // rows per band
+  int32_t h1, n1;  // long blocks: rows, count
+  int32_t h2, n2;  // short blocks: rows, count
+};
+
+__host__ __device__ inline Bands2D make_bands2d(int I0, int chunk) {
+  Bands2D g;
+  g.hb = (I0 + kXcds - 1) / kXcds;
+  g.h1 = chunk < 1 ? 1 : (chunk < g.hb ? chunk : g.hb);
+  if (g.h1 < 1) g.h1 = 1;
+  g.h2 = g.h1 >= 32 ? g.h1 / 2 : g.h1;
+  const int nfull = g.hb / g.h1;
+  g.n1 = nfull > 2 ? nfull - 2 : 0;
+  g.n2 = (g.hb - g.n1 * g.h1 + g.h2 - 1) / g.h2;
+  return g;
+}
+
+// Output rows [a, b) of block c of band x (empty when b <= a).  The fields
+// are read into values first: a conditional over two fields of the struct
+// would select between their addresses, and a struct indexed that way
+// cannot stay in registers.
+__host__ __device__ inline void band_rows2d(const Bands2D& g, int R, int I0, int x, int c, int& a, int& b) {
+  const int hb = g.hb, h1 = g.h1, n1 = g.n1, h2 = g.h2;
+  const int band0 = R + x * hb;
+  const int band1 = band0 + hb < I0 + R ? band0 + hb : I0 + R;
+  const bool lng = c < n1;
+  a = lng ? band0 + c * h1 : band0 + n1 * h1 + (c - n1) * h2;
+  const int e = a + (lng ? h1 : h2);
+  b = e < band1 ? e : band1;
+}
+
 // Geometry of one 2D launch, derived on the host.
 struct Sweep2DArgs {
   const void* src;
   void* dst;
   int32_t I0, I1;
   int32_t ntiles;   // tiles across axis 1
-  int32_t nwaves;   // ntiles * stream blocks
-  int32_t chunk;    // h_SN
+  int32_t nwaves;   // waves per band: ntiles * (n1 + n2)
+  Bands2D g;        // stream blocks (h_SN = g.h1)
   int32_t pad;
 };
 

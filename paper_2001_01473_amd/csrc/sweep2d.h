@@ -7,8 +7,10 @@
 // once and written once per BT time steps.  The tile overlaps its neighbours
 // by BT*R columns on each side; the valid width shrinks by 2R per level and
 // only the compute region of level BT is stored.  The axis-0 extent is cut
-// into stream blocks of `chunk` rows (h_SN, "Division of Streaming
-// Dimension"), each of which starts BT*R rows early to warm up the levels.
+// into stream blocks ("Division of Streaming Dimension"), each of which
+// starts BT*R rows early to warm up the levels; blocks are h_SN rows long
+// except for a tail of half-length blocks at the end of each XCD's band of
+// rows (Bands2D).
 //
 // MI355X mapping (differs from the paper's CUDA design):
 //  * one wave64 is one tile; lane l owns CPL consecutive columns, so the tile
@@ -16,7 +18,9 @@
 //    in-plane neighbours that live in another lane come from DPP whole-wave
 //    shifts (wave_shr:1 / wave_shl:1).  Lanes at the tile edge receive
 //    meaningless values, which only ever reach the overlap region that the
-//    shrinking valid width discards.
+//    shrinking valid width discards.  For plain float32 stars and 3x3 boxes
+//    the shift is folded into the term's FMA (fma_dpp), with the coefficient
+//    in a VGPR.
 //  * partial sums ("associative" stencils in the paper): a row arriving at
 //    level T is pushed at once into the 2R+1 output rows it contributes to,
 //    so a level holds only 2R pending accumulator rows and the arriving row is
@@ -56,9 +60,18 @@ struct alignas(16) EdgeStash {
   T cols[BT * R + 1][4][CPL];
 };
 
+// Coefficients (canonical order) of the in-row terms that read a neighbouring
+// lane: the centre row's off-centre points of a star, every column but the
+// centre one of a box.
+template <int R, bool BOX>
+constexpr bool folded_coef2d(int ci) {
+  return BOX ? ci % (2 * R + 1) != R : (ci >= R && ci <= 3 * R && ci != 2 * R);
+}
+
 template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR, bool EDGE>
 __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPack<T, npts(2, R, BOX)>& cf,
-                                             int lane, int tile, int chunk, EdgeStash<T, R, BT, CPL>* stash) {
+                                             int lane, int tile, int row_a, int row_b,
+                                             EdgeStash<T, R, BT, CPL>* stash) {
   constexpr int NA = 2 * R;         // pending output rows per level
   constexpr int NS = lcm_i(NA, NR); // steps per unrolled iteration (NR: rows in the load ring)
   constexpr int W = 64 * CPL;       // tile width (columns)
@@ -74,8 +87,6 @@ __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPac
   const int P0 = I0 + 2 * R, P1 = I1 + 2 * R;
   const int c_first = R + tile * C;      // first compute column
   const int col0 = c_first - LO;         // first column of the tile
-  const int row_a = R + chunk * a.chunk; // first output row of this stream block
-  const int row_b = min(row_a + a.chunk, I0 + R);
   const int colL = col0 + lane * CPL;    // first column owned by this lane
 
   // Stores: a lane whose CPL cells all lie in the compute region writes them
@@ -127,6 +138,16 @@ __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPac
     }
   };
 
+  // Folded lane shifts: the coefficients of in-row terms that read a
+  // neighbouring lane live in VGPRs.
+  constexpr int NP = npts(2, R, BOX);
+  constexpr bool FOLD = ACC == 0 && std::is_same_v<T, float> && (!BOX || R == 1);
+  T cv[NP];
+  if constexpr (FOLD)
+    sfor<NP>([&](auto I) S5D_INL {
+      if constexpr (folded_coef2d<R, BOX>(I)) cv[I] = to_vgpr(cf.c[I]);
+    });
+
   Accum<T, ACC> acc[BT][NA][CPL];
   using RowV = T __attribute__((ext_vector_type(CPL)));
   RowV ringv[NR];
@@ -173,22 +194,36 @@ __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPac
           E[R + CPL + J] = lane_from_upper(cur[J]);
         });
 
+        // one in-row term: coefficient ci times extended-row cell e
+        auto term = [&](Accum<T, ACC>& acc_k, auto CI, auto EI, auto FIRST) S5D_INL {
+          constexpr int ci = CI, e = EI;
+          constexpr bool first = FIRST;
+          if constexpr (FOLD && (e < R || e >= R + CPL)) {
+            constexpr bool shr = e < R;  // from lane l-1, else lane l+1
+            constexpr int src = shr ? CPL - R + e : e - R - CPL;
+            if constexpr (first) acc_k.s = mul_dpp<shr>(cur[src], cv[ci]);
+            else acc_k.s = fma_dpp<shr>(acc_k.s, cur[src], cv[ci]);
+          } else if constexpr (first) {
+            acc_k.first(cf.c[ci], E[e]);
+          } else {
+            acc_k.add(cf.c[ci], E[e]);
+          }
+        };
         // contribution of the arriving row to the output d0 rows before it
         auto add_row = [&](auto D0, Accum<T, ACC>& acc_k, auto K, auto FIRST) S5D_INL {
           constexpr int d0 = D0;
           constexpr bool first = FIRST;
           if constexpr (BOX) {
             sfor<2 * R + 1>([&](auto D1) S5D_INL {
-              constexpr int ci = (d0 + R) * (2 * R + 1) + D1;
-              if constexpr (first && D1 == 0) acc_k.first(cf.c[ci], E[K + D1]);
-              else acc_k.add(cf.c[ci], E[K + D1]);
+              term(acc_k, ic<(d0 + R) * (2 * R + 1) + D1>{}, ic<K + D1>{},
+                   std::integral_constant<bool, first && D1 == 0>{});
             });
           } else if constexpr (d0 != 0) {
             constexpr int ci = d0 < 0 ? d0 + R : 3 * R + d0;
             if constexpr (first) acc_k.first(cf.c[ci], cur[K]);
             else acc_k.add(cf.c[ci], cur[K]);
           } else {
-            sfor<2 * R + 1>([&](auto D1) S5D_INL { acc_k.add(cf.c[R + D1], E[K + D1]); });
+            sfor<2 * R + 1>([&](auto D1) S5D_INL { term(acc_k, ic<R + D1>{}, ic<K + D1>{}, std::false_type{}); });
           }
         };
 
@@ -246,7 +281,8 @@ __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPac
   for (int it = 1; it < niter; ++it) iteration(s0 + it * NS);
 }
 
-// Workgroup lb of one grid's launch: kWavesPerBlock waves, one tile each.
+// Workgroup lb of one grid's launch: kWavesPerBlock waves, one tile each, of
+// band lb % kXcds (the XCD the workgroup runs on in a launch of its own).
 template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
 __device__ __forceinline__ void sweep2d_block(const Sweep2DArgs& a, const CoefPack<T, npts(2, R, BOX)>& cf, int lb,
                                               EdgeStash<T, R, BT, CPL>* stash) {
@@ -256,29 +292,30 @@ __device__ __forceinline__ void sweep2d_block(const Sweep2DArgs& a, const CoefPa
   static_assert(R <= CPL, "the lane exchange reaches one neighbouring lane only");
   static_assert(C >= 1, "tile narrower than its overlap");
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wid = lb * kWavesPerBlock + wib;
+  const int x = lb % kXcds;
+  const int wid = (lb / kXcds) * kWavesPerBlock + wib;  // wave within the band
   if (wid >= a.nwaves) return;
   const int lane = threadIdx.x & 63;
   const int tile = wid % a.ntiles;
-  const int chunk = wid / a.ntiles;
+  int row_a, row_b;
+  band_rows2d(a.g, R, a.I0, x, wid / a.ntiles, row_a, row_b);
+  if (row_b <= row_a) return;
 
   const int P1 = a.I1 + 2 * R;
   const int col0 = R + tile * C - LO;
-  const int row_a = R + chunk * a.chunk;
-  const int row_b = min(row_a + a.chunk, a.I0 + R);
   const bool edge = col0 < 0 || col0 + W > P1 || row_a - (BT - 1) * R < R ||
                     row_b + (BT - 1) * R > a.I0 + R;
   if (edge)
-    sweep2d_body<T, ACC, R, BOX, BT, CPL, NR, true>(a, cf, lane, tile, chunk, &stash[wib]);
+    sweep2d_body<T, ACC, R, BOX, BT, CPL, NR, true>(a, cf, lane, tile, row_a, row_b, &stash[wib]);
   else
-    sweep2d_body<T, ACC, R, BOX, BT, CPL, NR, false>(a, cf, lane, tile, chunk, &stash[wib]);
+    sweep2d_body<T, ACC, R, BOX, BT, CPL, NR, false>(a, cf, lane, tile, row_a, row_b, &stash[wib]);
 }
 
 template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void sweep2d_kernel(Sweep2DArgs a,
                                                                     CoefPack<T, npts(2, R, BOX)> cf) {
   __shared__ EdgeStash<T, R, BT, CPL> stash[kWavesPerBlock];
-  sweep2d_block<T, ACC, R, BOX, BT, CPL, NR>(a, cf, xcd_logical_block(blockIdx.x, gridDim.x), stash);
+  sweep2d_block<T, ACC, R, BOX, BT, CPL, NR>(a, cf, blockIdx.x, stash);
 }
 
 // One grid of a batched launch: its geometry and coefficients.
@@ -297,8 +334,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void sweep2d_batch_kernel(
   __shared__ EdgeStash<T, R, BT, CPL> stash[kWavesPerBlock];
   const BlockMap m = map[xcd_logical_block(blockIdx.x, gridDim.x)];
   const Item2D<T, npts(2, R, BOX)>& it = items[__builtin_amdgcn_readfirstlane(m.item)];
-  const Sweep2DArgs a = it.a;
-  const CoefPack<T, npts(2, R, BOX)> cf = it.cf;
+  const Sweep2DArgs a = uniform_copy(it.a);
+  const CoefPack<T, npts(2, R, BOX)> cf = uniform_copy(it.cf);
   sweep2d_block<T, ACC, R, BOX, BT, CPL, NR>(a, cf, __builtin_amdgcn_readfirstlane(m.block), stash);
 }
 
@@ -312,19 +349,25 @@ Sweep2DArgs make_args2d(const Round2D& rd, CoefPack<T, npts(2, R, BOX)>& cf) {
   a.dst = rd.dst;
   a.I0 = rd.I0;
   a.I1 = rd.I1;
-  a.chunk = rd.chunk;
+  a.g = make_bands2d(rd.I0, rd.chunk);
   a.ntiles = (rd.I1 + C - 1) / C;
-  const int nchunks = (rd.I0 + rd.chunk - 1) / rd.chunk;
-  a.nwaves = a.ntiles * nchunks;
+  const int64_t nw = static_cast<int64_t>(a.ntiles) * (a.g.n1 + a.g.n2);
+  a.nwaves = nw > INT32_MAX / kXcds ? 0 : static_cast<int32_t>(nw);
   a.pad = 0;
   return a;
+}
+
+// Workgroups of a launch: kXcds bands of ceil(nwaves / kWavesPerBlock).
+inline int blocks2d(const Sweep2DArgs& a) {
+  return kXcds * ((a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock);
 }
 
 template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
 hipError_t launch_sweep2d(const Round2D& rd) {
   CoefPack<T, npts(2, R, BOX)> cf;
   const Sweep2DArgs a = make_args2d<T, R, BOX, BT, CPL>(rd, cf);
-  const int nblk = (a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (a.nwaves == 0) return hipErrorInvalidConfiguration;
+  const int nblk = blocks2d(a);
   hipLaunchKernelGGL((sweep2d_kernel<T, ACC, R, BOX, BT, CPL, NR>), dim3(nblk), dim3(64 * kWavesPerBlock), 0,
                      rd.stream, a, cf);
   return hipGetLastError();
@@ -335,7 +378,7 @@ int fill_item2d(void* item, const Round2D& rd) {
   Item2D<T, npts(2, R, BOX)> it;
   it.a = make_args2d<T, R, BOX, BT, CPL>(rd, it.cf);
   __builtin_memcpy(item, &it, sizeof(it));
-  return (it.a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
+  return blocks2d(it.a);
 }
 
 template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>

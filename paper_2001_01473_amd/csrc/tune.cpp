@@ -27,18 +27,20 @@
 namespace s5d {
 namespace {
 
-// Device rates.  VALU lane-operations per clock per CU: 128 in float32, 64
-// in float64 (MI355X's published vector peaks, 157.3 and 78.6 TFLOP/s, at 256
-// CUs and 2.4 GHz; the float32 rate is reached by unpacked operations too).
-// HBM: the practical streaming rate (a plain device copy sustains about
-// 6 TB/s of the 8 TB/s peak).  LDS: 128 bytes per clock per CU.
+// Device rates.  VALU lane-operations per clock per CU: 64 in float32 and in
+// float64.  The kernels are built without packed float32 instructions, and
+// unpacked float32 FMAs issue at the float64 rate: 64 lanes per clock per CU
+// (78.6e12 flop/s at 256 CUs and 2.4 GHz; MI355X's published 157.3 TFLOP/s
+// float32 peak counts packed operations).  HBM: the practical streaming rate
+// (a plain device copy sustains about 6 TB/s of the 8 TB/s peak).  LDS: 128
+// bytes per clock per CU.
 struct Rates {
-  double valu, hbm, lds;  // valu: float32 lane-operations per second
+  double valu, hbm, lds;  // valu: lane-operations per second
   int cus;
 };
 
 Rates device_rates() {
-  Rates r{256 * 128 * 2.4e9, 6.0e12, 256 * 128 * 2.4e9, 256};
+  Rates r{256 * 64 * 2.4e9, 6.0e12, 256 * 128 * 2.4e9, 256};
   int dev = 0, cus = 0, khz = 0;
   if (hipGetDevice(&dev) == hipSuccess &&
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
@@ -46,7 +48,7 @@ Rates device_rates() {
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeClockRate, dev) == hipSuccess && khz > 0)
       clock = khz * 1e3;
     r.cus = cus;
-    r.valu = cus * 128.0 * clock;
+    r.valu = cus * 64.0 * clock;
     r.lds = cus * 128.0 * clock;
   }
   (void)hipGetLastError();
@@ -64,9 +66,11 @@ double ops_per_cell(const s5d_plan* p, int cpl) {
   double ops = p->kind == KIND_F32_COMP ? 9.0 * (n - 1) + 3.0 : static_cast<double>(n);
   // lane exchange: R cells from each neighbouring lane for every row that
   // needs in-row neighbours (one row for a star, 2r+1 rows or planes x rows
-  // for a box), by 32-bit DPP moves
+  // for a box), by 32-bit DPP moves -- except in the 2D plain float32 star
+  // and 3x3 box kernels, which fold the shift into the FMA
   const int rows_ext = box ? (nd == 2 ? 2 * r + 1 : (2 * r + 1) * (2 * r + 1)) : (nd == 2 ? 1 : 1);
-  ops += static_cast<double>(rows_ext) * 2.0 * r * words / cpl;
+  const bool folded = nd == 2 && p->kind == KIND_F32 && (!box || r == 1);
+  if (!folded) ops += static_cast<double>(rows_ext) * 2.0 * r * words / cpl;
   ops += 0.5;  // loads, stores, ring bookkeeping, per cell
   return ops;
 }
@@ -89,7 +93,8 @@ RoundModel model_round2d(const s5d_plan* p, int bt) {
   const int LO = overlap_left(bt, r, p->elem), C = compute_width(W, bt, r, p->elem);
   const int64_t I0 = p->d.interior[0], I1 = p->d.interior[1], P0 = I0 + 2 * r, P1 = I1 + 2 * r;
   const int64_t h = p->tun.stream_chunk, w = p->elem;
-  const int64_t ntiles = (I1 + C - 1) / C, nch = (I0 + h - 1) / h;
+  const Bands2D g = make_bands2d(static_cast<int>(I0), static_cast<int>(h));
+  const int64_t ntiles = (I1 + C - 1) / C;
   int64_t cols_read = 0, cols_written = 0;
   for (int64_t t = 0; t < ntiles; ++t) {
     const int64_t c0 = r + t * C;
@@ -97,14 +102,19 @@ RoundModel model_round2d(const s5d_plan* p, int bt) {
     cols_written += std::min<int64_t>(C, I1 - t * C);
   }
   double rows_read = 0, rows_comp = 0;
-  for (int64_t c = 0; c < nch; ++c) {
-    const int64_t a = r + c * h, b = std::min<int64_t>(a + h, I0 + r);
-    rows_read += clip(a - static_cast<int64_t>(bt) * r, b + static_cast<int64_t>(bt) * r, P0);
-    for (int T = 1; T <= bt; ++T) rows_comp += static_cast<double>(b - a) + 2.0 * (bt - T) * r;
-  }
+  int64_t blocks = 0;  // non-empty stream blocks
+  for (int x = 0; x < kXcds; ++x)
+    for (int c = 0; c < g.n1 + g.n2; ++c) {
+      int a = 0, b = 0;
+      band_rows2d(g, r, static_cast<int>(I0), x, c, a, b);
+      if (b <= a) continue;
+      ++blocks;
+      rows_read += clip(a - static_cast<int64_t>(bt) * r, b + static_cast<int64_t>(bt) * r, P0);
+      for (int T = 1; T <= bt; ++T) rows_comp += static_cast<double>(b - a) + 2.0 * (bt - T) * r;
+    }
   m.gm = (rows_read * cols_read + static_cast<double>(I0) * cols_written) * w;
   m.ops = rows_comp * W * ntiles * ops_per_cell(p, cpl);
-  m.wgs = (ntiles * nch + kWavesPerBlock - 1) / kWavesPerBlock;
+  m.wgs = (ntiles * blocks + kWavesPerBlock - 1) / kWavesPerBlock;
   const int occ = p->by_bt[bt].occupancy ? p->by_bt[bt].occupancy() : 0;
   m.wg_per_cu = occ > 0 ? occ : 2;
   return m;
@@ -202,7 +212,7 @@ s5d_status model_plan(const s5d_plan* p, s5d_model* out) {
                                       : (p->d.ndim == 3 ? model_round3d(p, bt) : model_round2d(p, bt)))
                .first;
     const RoundModel& m = it->second;
-    const double valu = p->elem == 8 ? rt.valu / 2 : rt.valu;  // float64 at half rate
+    const double valu = rt.valu;  // float32 (unpacked) and float64 issue at one rate
     const double ta = m.ops / valu, tg = m.gm / rt.hbm, tl = m.lds / rt.lds;
     // slot efficiency: with fewer workgroups than resident slots the machine
     // is part idle; otherwise the last workgroups finish unevenly, a tail of

@@ -21,3 +21,27 @@ def overlap_right(bt, r, elem):
 
 def compute_width(w, bt, r, elem):
     return w - overlap_left(bt, r, elem) - overlap_right(bt, r, elem)
+
+
+def stream_blocks_2d(I0, r, chunk, xcds=8):
+    """Output-row ranges [a, b) of a 2D launch's stream blocks: 8 bands of
+    ceil(I0 / 8) rows (one per XCD); a band holds blocks of h = min(chunk,
+    band) rows, and when it has room for more than two, its last rows go in
+    blocks of h // 2 rows (h >= 32) so each XCD ends on short blocks."""
+    hb = -(-I0 // xcds)
+    h1 = max(1, min(chunk, hb))
+    h2 = h1 // 2 if h1 >= 32 else h1
+    n1 = max(0, hb // h1 - 2)
+    out = []
+    for x in range(xcds):
+        lo, hi = r + x * hb, min(r + (x + 1) * hb, I0 + r)
+        a = lo
+        for _ in range(n1):
+            if a >= hi:
+                break
+            out.append((a, min(a + h1, hi)))
+            a += h1
+        while a < hi:
+            out.append((a, min(a + h2, hi)))
+            a += h2
+    return out
