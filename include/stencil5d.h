@@ -103,11 +103,14 @@ typedef struct s5d_tuning {
 } s5d_tuning;
 
 /* Kernel families (s5d_tuning.kernel). */
-#define S5D_KERNEL_AUTO 0    /* temporally blocked where compiled, else direct */
+#define S5D_KERNEL_AUTO 0    /* temporally blocked where compiled, else direct; direct
+                                also for a 2D plain-accumulation star or box of
+                                radius <= 2 whose tuning asks for bt = 1 and nothing
+                                else (faster than blocking at depth 1) */
 #define S5D_KERNEL_BLOCKED 1 /* b_T fused steps per launch (AN5D "Execution Model") */
-#define S5D_KERNEL_DIRECT 2  /* one step per launch from an LDS-staged tile; covers every
-                                radius 1..4 and shape, for stencils whose blocked state
-                                does not fit a lane (the plan's bt is 1) */
+#define S5D_KERNEL_DIRECT 2  /* one step per launch, every radius 1..4 and shape: 2D stars
+                                and boxes of radius <= 2 stream whole rows, the others
+                                work from an LDS-staged tile (the plan's bt is 1) */
 
 typedef struct s5d_plan s5d_plan; /* opaque; immutable once created */
 

@@ -578,8 +578,13 @@ s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_p
   }
   const bool no_blocking = req.bt <= 1 && req.cells_per_lane == 0 && req.rows_per_wave == 0 && req.tile0 == 0 &&
                            req.tile1 == 0 && req.stream_chunk == 0;
+  // b_T = 1 asked for a 2D stencil: the row-streaming direct kernel (plain
+  // accumulation; stars and boxes of radius <= 2) is faster than the blocked
+  // kernel at depth 1
+  const bool stream_bt1 = req.kernel == S5D_KERNEL_AUTO && no_blocking && req.bt == 1 && d.ndim == 2 &&
+                          p->kind != KIND_F32_COMP && (!box || r <= 2);
   if (st != S5D_OK) {
-    if (req.kernel == S5D_KERNEL_DIRECT ||
+    if (req.kernel == S5D_KERNEL_DIRECT || stream_bt1 ||
         (req.kernel == S5D_KERNEL_AUTO && no_blocking && req.bt == 0 && prefer_direct(p->kind, d.ndim, box, r))) {
       st = plan_direct(p, req, box, r);
     } else {

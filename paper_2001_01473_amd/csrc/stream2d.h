@@ -5,11 +5,14 @@
 // thread reads its CPL cells and the r cells on either side from the 2r+1
 // rows p-r .. p+r straight from global memory and sums every cell's terms in
 // the canonical (d0, d1) order, with the same accumulation policy as the
-// blocked kernels -- so both give the same bits.  Consecutive workgroups of an
-// XCD take consecutive segments and rows, so the rows a workgroup shares with
-// its neighbours are still in that XCD's L2: HBM sees about one read and one
-// write per cell, in address order, like a plain streaming copy.  No LDS, no
-// barrier.
+// blocked kernels -- so both give the same bits.  Workgroups run in plain
+// dispatch order: at any moment the whole machine works on one window of
+// consecutive rows, which the memory system streams like a plain copy; the
+// 2r re-reads of each row are served by the caches (measured on MI355X: 12 %
+// faster than giving each XCD its own contiguous band of rows).  Float32 star
+// stencils take the in-row neighbours from the neighbouring lanes (DPP; the
+// wave's edge lanes load theirs), and results are written with non-temporal
+// stores (they are not read again in this launch).  No LDS, no barrier.
 #pragma once
 
 #include "kcommon.h"
@@ -44,9 +47,29 @@ __device__ __forceinline__ void stream2d_block(const Stream2DArgs& a, int lb) {
   const T* __restrict__ c = static_cast<const T*>(a.coef);
   // the thread's cells and their r neighbours on each side, per stencil row;
   // columns beyond the padded row read 0 (they feed no stored cell)
+  constexpr bool DPPH = std::is_same_v<T, float> && !BOX;
   auto load_row = [&](T (&x)[CPL + 2 * R], int row, bool full) S5D_INL {
     const T* rp = src + static_cast<int64_t>(row) * P1;
-    if (c0 + CPL + R <= P1) {
+    if constexpr (DPPH) {
+      // own cells (a vector, or cell by cell at the row end); then, with
+      // every lane active, the neighbours from the adjacent lanes
+      if (c0 + CPL <= P1) {
+        const LaneVec<T, CPL> v = *reinterpret_cast<const LaneVec<T, CPL>*>(rp + c0);
+        sfor<CPL>([&](auto K) S5D_INL { x[R + K] = v.v[K]; });
+      } else {
+        sfor<CPL>([&](auto K) S5D_INL { x[R + K] = c0 + K < P1 ? rp[c0 + K] : T(0); });
+      }
+      if (full) {
+        sfor<R>([&](auto J) S5D_INL {
+          x[J] = lane_from_lower(x[CPL + J]);
+          x[R + CPL + J] = lane_from_upper(x[R + J]);
+        });
+        const int lane = threadIdx.x & 63;
+        if (lane == 0) sfor<R>([&](auto J) S5D_INL { x[J] = rp[c0 - R + J]; });
+        if (lane == 63)
+          sfor<R>([&](auto J) S5D_INL { x[R + CPL + J] = c0 + CPL + J < P1 ? rp[c0 + CPL + J] : T(0); });
+      }
+    } else if (c0 + CPL + R <= P1) {
       const LaneVec<T, CPL> v = *reinterpret_cast<const LaneVec<T, CPL>*>(rp + c0);
       sfor<CPL>([&](auto K) S5D_INL { x[R + K] = v.v[K]; });
       if (full)
@@ -96,9 +119,10 @@ __device__ __forceinline__ void stream2d_block(const Stream2DArgs& a, int lb) {
   sfor<CPL>([&](auto K) S5D_INL { out[K] = acc[K].value(); });
   T* wp = dst + static_cast<int64_t>(p) * P1;
   if (c0 + CPL <= a.I1 + R) {
-    LaneVec<T, CPL> v;
-    sfor<CPL>([&](auto K) S5D_INL { v.v[K] = out[K]; });
-    *reinterpret_cast<LaneVec<T, CPL>*>(wp + c0) = v;
+    using VT = T __attribute__((ext_vector_type(CPL), aligned(sizeof(T))));  // element-aligned address
+    VT v;
+    sfor<CPL>([&](auto K) S5D_INL { v[+K] = out[K]; });
+    __builtin_nontemporal_store(v, reinterpret_cast<VT*>(wp + c0));
   } else {
     sfor<CPL>([&](auto K) S5D_INL {
       if (c0 + K < a.I1 + R) wp[c0 + K] = out[K];
@@ -108,7 +132,7 @@ __device__ __forceinline__ void stream2d_block(const Stream2DArgs& a, int lb) {
 
 template <typename T, int ACC, int R, bool BOX>
 __global__ __launch_bounds__(256) void stream2d_kernel(Stream2DArgs a) {
-  stream2d_block<T, ACC, R, BOX>(a, xcd_logical_block(blockIdx.x, gridDim.x));
+  stream2d_block<T, ACC, R, BOX>(a, blockIdx.x);
 }
 
 template <typename T, int ACC, int R, bool BOX>

@@ -80,7 +80,7 @@ def test_model2d_counts_match_brute_force(I, r, box, dtype, bt, cpl, h):
 def test_model_regimes():
     # float32 5-point star at b_T = 1 moves 8 bytes per update and does ~6
     # operations: bound by HBM
-    p = _plan(2, 1, False, "f32", (16384, 16384), 10, bt=1)
+    p = _plan(2, 1, False, "f32", (16384, 16384), 10, bt=1, kernel="blocked")
     assert p.model()["bound"] == "hbm"
     p.close()
     # compensated 25-point box: ~220 operations per update, bound by the ALU
@@ -88,7 +88,7 @@ def test_model_regimes():
     assert p.model()["bound"] == "alu"
     p.close()
     # deeper temporal blocking moves fewer bytes per update
-    a = _plan(2, 1, False, "f32", (16384, 16384), 100, bt=1).model()
+    a = _plan(2, 1, False, "f32", (16384, 16384), 100, bt=1, kernel="blocked").model()
     b = _plan(2, 1, False, "f32", (16384, 16384), 100, bt=10).model()
     assert b["hbm_bytes"] < a["hbm_bytes"] / 5
     assert b["seconds"] < a["seconds"]
