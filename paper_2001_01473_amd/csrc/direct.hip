@@ -25,7 +25,7 @@ Kernel2D make2d() {
                     &occupancy_stream2d<T, ACC, R, BOX>,
                     0,
                     1,
-                    256 * stream2d_cpl<T>(),
+                    kStreamThreads * stream2d_cpl<T>(),
                     &fill_stream2d<T>,
                     &launch_stream2d_batch<T, ACC, R, BOX>,
                     static_cast<int>(sizeof(Stream2DArgs))};

@@ -1,7 +1,7 @@
 // Direct 2D kernel: one time step per launch, streaming whole rows.
 //
 // Workgroup (row p, segment s) computes the cells of interior row p in
-// columns [R + s*SEG, R + (s+1)*SEG), SEG = 256 threads x CPL cells.  Each
+// columns [R + s*SEG, R + (s+1)*SEG), SEG = kStreamThreads x CPL cells.  Each
 // thread reads its CPL cells and the r cells on either side from the 2r+1
 // rows p-r .. p+r straight from global memory and sums every cell's terms in
 // the canonical (d0, d1) order, with the same accumulation policy as the
@@ -9,10 +9,11 @@
 // dispatch order: at any moment the whole machine works on one window of
 // consecutive rows, which the memory system streams like a plain copy; the
 // 2r re-reads of each row are served by the caches (measured on MI355X: 12 %
-// faster than giving each XCD its own contiguous band of rows).  Float32 star
-// stencils take the in-row neighbours from the neighbouring lanes (DPP; the
-// wave's edge lanes load theirs), and results are written with non-temporal
-// stores (they are not read again in this launch).  No LDS, no barrier.
+// faster than giving each XCD its own contiguous band of rows).  Star
+// stencils take the in-row neighbours of the centre row from the neighbouring
+// lanes (DPP); the wave's two edge lanes take theirs from two wave-uniform
+// loads, so no lane diverges.  Results are written with non-temporal stores
+// (they are not read again in this launch).  No LDS, no barrier.
 #pragma once
 
 #include "kcommon.h"
@@ -28,6 +29,8 @@ struct Stream2DArgs {
   int32_t pad;
 };
 
+constexpr int kStreamThreads = 512;  // threads per workgroup (measured best of 128..1024)
+
 template <typename T>
 constexpr int stream2d_cpl() {
   return 16 / static_cast<int>(sizeof(T));  // one 16-byte vector per thread
@@ -36,18 +39,20 @@ constexpr int stream2d_cpl() {
 template <typename T, int ACC, int R, bool BOX>
 __device__ __forceinline__ void stream2d_block(const Stream2DArgs& a, int lb) {
   constexpr int CPL = stream2d_cpl<T>();
-  constexpr int SEG = 256 * CPL;
+  constexpr int SEG = kStreamThreads * CPL;
   constexpr int E = 2 * R + 1;
   const int P1 = a.I1 + 2 * R;
   const int p = R + lb / a.nseg;            // interior row
   const int seg = lb - (lb / a.nseg) * a.nseg;
   const int c0 = R + seg * SEG + static_cast<int>(threadIdx.x) * CPL;  // first column of this thread
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+  const int wc0 = R + seg * SEG + wave * 64 * CPL;                      // first column of this wave
   const T* __restrict__ src = static_cast<const T*>(a.src);
   T* __restrict__ dst = static_cast<T*>(a.dst);
   const T* __restrict__ c = static_cast<const T*>(a.coef);
   // the thread's cells and their r neighbours on each side, per stencil row;
   // columns beyond the padded row read 0 (they feed no stored cell)
-  constexpr bool DPPH = std::is_same_v<T, float> && !BOX;
+  constexpr bool DPPH = !BOX && R <= CPL;  // a lane shift reaches one neighbouring lane only
   auto load_row = [&](T (&x)[CPL + 2 * R], int row, bool full) S5D_INL {
     const T* rp = src + static_cast<int64_t>(row) * P1;
     if constexpr (DPPH) {
@@ -64,10 +69,16 @@ __device__ __forceinline__ void stream2d_block(const Stream2DArgs& a, int lb) {
           x[J] = lane_from_lower(x[CPL + J]);
           x[R + CPL + J] = lane_from_upper(x[R + J]);
         });
+        // the wave's edge lanes: wave-uniform loads (clamped into the row
+        // for a wave past its end, whose cells are not stored)
         const int lane = threadIdx.x & 63;
-        if (lane == 0) sfor<R>([&](auto J) S5D_INL { x[J] = rp[c0 - R + J]; });
-        if (lane == 63)
-          sfor<R>([&](auto J) S5D_INL { x[R + CPL + J] = c0 + CPL + J < P1 ? rp[c0 + CPL + J] : T(0); });
+        sfor<R>([&](auto J) S5D_INL {
+          const int lc = wc0 - R + J, rc = wc0 + 64 * CPL + J;
+          const T lft = rp[lc < P1 ? lc : P1 - 1];
+          const T rgt = rp[rc < P1 ? rc : P1 - 1];
+          x[J] = lane == 0 ? lft : x[J];
+          x[R + CPL + J] = lane == 63 ? (rc < P1 ? rgt : T(0)) : x[R + CPL + J];
+        });
       }
     } else if (c0 + CPL + R <= P1) {
       const LaneVec<T, CPL> v = *reinterpret_cast<const LaneVec<T, CPL>*>(rp + c0);
@@ -131,12 +142,12 @@ __device__ __forceinline__ void stream2d_block(const Stream2DArgs& a, int lb) {
 }
 
 template <typename T, int ACC, int R, bool BOX>
-__global__ __launch_bounds__(256) void stream2d_kernel(Stream2DArgs a) {
+__global__ __launch_bounds__(kStreamThreads) void stream2d_kernel(Stream2DArgs a) {
   stream2d_block<T, ACC, R, BOX>(a, blockIdx.x);
 }
 
 template <typename T, int ACC, int R, bool BOX>
-__global__ __launch_bounds__(256) void stream2d_batch_kernel(const Stream2DArgs* __restrict__ items,
+__global__ __launch_bounds__(kStreamThreads) void stream2d_batch_kernel(const Stream2DArgs* __restrict__ items,
                                                              const BlockMap* __restrict__ map) {
   const BlockMap m = map[xcd_logical_block(blockIdx.x, gridDim.x)];
   const Stream2DArgs a = items[__builtin_amdgcn_readfirstlane(m.item)];
@@ -145,7 +156,7 @@ __global__ __launch_bounds__(256) void stream2d_batch_kernel(const Stream2DArgs*
 
 template <typename T>
 int64_t stream2d_args(Stream2DArgs& a, const Round2D& rd) {
-  constexpr int SEG = 256 * stream2d_cpl<T>();
+  constexpr int SEG = kStreamThreads * stream2d_cpl<T>();
   a.src = rd.src;
   a.dst = rd.dst;
   a.coef = rd.dcoef;
@@ -162,7 +173,7 @@ hipError_t launch_stream2d(const Round2D& rd) {
   Stream2DArgs a;
   const int64_t nblk = stream2d_args<T>(a, rd);
   if (nblk == 0) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((stream2d_kernel<T, ACC, R, BOX>), dim3(static_cast<unsigned>(nblk)), dim3(256), 0, rd.stream,
+  hipLaunchKernelGGL((stream2d_kernel<T, ACC, R, BOX>), dim3(static_cast<unsigned>(nblk)), dim3(kStreamThreads), 0, rd.stream,
                      a);
   return hipGetLastError();
 }
@@ -177,7 +188,7 @@ int fill_stream2d(void* item, const Round2D& rd) {
 
 template <typename T, int ACC, int R, bool BOX>
 hipError_t launch_stream2d_batch(const void* items, const BlockMap* map, int nblocks, hipStream_t stream) {
-  hipLaunchKernelGGL((stream2d_batch_kernel<T, ACC, R, BOX>), dim3(nblocks), dim3(256), 0, stream,
+  hipLaunchKernelGGL((stream2d_batch_kernel<T, ACC, R, BOX>), dim3(nblocks), dim3(kStreamThreads), 0, stream,
                      static_cast<const Stream2DArgs*>(items), map);
   return hipGetLastError();
 }
@@ -185,7 +196,7 @@ hipError_t launch_stream2d_batch(const void* items, const BlockMap* map, int nbl
 template <typename T, int ACC, int R, bool BOX>
 int occupancy_stream2d() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stream2d_kernel<T, ACC, R, BOX>, 256, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stream2d_kernel<T, ACC, R, BOX>, kStreamThreads, 0) != hipSuccess)
     return 0;
   return nb;
 }

@@ -129,11 +129,11 @@ RoundModel model_round_direct(const s5d_plan* p) {
   const int64_t w = p->elem;
   double cells = 1, staged = 1;
   int64_t tiles = 1;
-  // 2D: one row of 256 x (16 bytes / w) cells per workgroup, no LDS (box
+  // 2D: one row of 512 x (16 bytes / w) cells per workgroup, no LDS (box
   // radius 3-4: LDS tiles of 16 x 64); 3D: LDS tiles of 4 x 8 x (64, or 32
   // for r >= 3) cells
   const bool lds2 = p->d.shape == S5D_BOX && r >= 3;
-  const int dims2[2] = {lds2 ? 16 : 1, lds2 ? 64 : 256 * 16 / static_cast<int>(w)};
+  const int dims2[2] = {lds2 ? 16 : 1, lds2 ? 64 : 512 * 16 / static_cast<int>(w)};
   const int dims3[3] = {4, 8, r >= 3 ? 32 : 64};
   for (int a = 0; a < nd; ++a) {
     const int64_t I = p->d.interior[a];

@@ -101,3 +101,26 @@ def test_auto_falls_back_to_direct():
     got, info = run_gpu(case.grid, radius=2, box=True, coeffs=case.coeffs, steps=3)
     assert info["kernel"] == 2
     assert max(rel_errors(got, ref)) <= 1e-12
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+@pytest.mark.parametrize("s", [(2, 1, False), (2, 2, False), (2, 1, True), (2, 2, True)], ids=_sid)
+def test_row_streaming_spans_segments(s, dt):
+    """The row-streaming kernel on rows of several workgroup segments (512
+    threads x one 16-byte vector) plus a ragged tail, and on a row shorter
+    than one wave: the same bits as the blocked kernel at b_T = 1, and float64
+    within 1e-12 of the oracle."""
+    nd, r, box = s
+    seg = 512 * (16 // np.dtype(dt).itemsize)
+    T = 3
+    for interior in ((13, 2 * seg + 389), (6, 37)):
+        case = si.make_case(91 + r, nd, r, box, interior, T)
+        c_in, g_in = case.as_dtype(dt)
+        say("row streaming", _sid(s), dt.__name__, interior)
+        a, ia = run_gpu(g_in, radius=r, box=box, coeffs=case.coeffs, steps=T, bt=1)
+        b, ib = run_gpu(g_in, radius=r, box=box, coeffs=case.coeffs, steps=T, bt=1, kernel="blocked")
+        assert ia["kernel"] == 2 and ib["kernel"] == 1
+        np.testing.assert_array_equal(a, b)
+        if dt == np.float64:
+            ref = oracle.sweep(g_in, radius=r, box=box, coeffs=c_in, steps=T)
+            assert max(rel_errors(a, ref)) <= 1e-12
