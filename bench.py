@@ -538,6 +538,22 @@ def bench_accuracy():
     return out
 
 
+def summarize_pmc(d, kernel):
+    """Markdown table of per-dispatch counter averages (rocprofv3 --pmc CSV)."""
+    import csv
+    import glob
+    vals = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if kernel in r["Kernel_Name"]:
+                vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    print("| counter | dispatches | average per dispatch |")
+    print("|---|---|---|")
+    for k in sorted(vals):
+        v = vals[k]
+        print("| %s | %d | %.6g |" % (k, len(v), sum(v) / len(v)))
+
+
 def ingest_counters(fetch_dir, write_dir, out_json, out_md, command):
     """Per-launch HBM traffic of the headline kernel from two rocprofv3 --pmc
     runs of `bench.py --probe` (FETCH_SIZE, then WRITE_SIZE), each scaled by what
@@ -605,13 +621,18 @@ def probe(args):
     print("probe copy bytes_read=%d bytes_written=%d" % (nbytes, nbytes), flush=True)
     del x, y
     import paper_2001_01473_amd as s5d
-    shape = si.padded_shape((N, N), 1)
+    nd = 3 if args.probe3d else 2
+    interior = (N3,) * 3 if nd == 3 else (N, N)
+    shape = si.padded_shape(interior, 1)
     b0 = torch.full(shape, 0.5, dtype=torch.float32, device="cuda:0")
     b1 = torch.empty_like(b0)
     # 2*b_T steps = two launches of the b_T kernel per run
-    plan = s5d.Plan(ndim=2, radius=1, box=False, dtype="f32", interior=(N, N), steps=2 * args.bt,
-                    coeffs=si.random_coeffs(np.random.default_rng(si.workload_seed(1)), 5),
-                    bt=args.bt)
+    tuning = {"bt": args.bt} if nd == 2 else {}
+    bt = args.bt if nd == 2 else s5d.Plan(ndim=3, radius=1, box=False, dtype="f32", interior=interior,
+                                          steps=1000, coeffs=np.full(7, 1 / 7)).query()["bt"]
+    plan = s5d.Plan(ndim=nd, radius=1, box=False, dtype="f32", interior=interior, steps=2 * bt,
+                    coeffs=si.random_coeffs(np.random.default_rng(si.workload_seed(nd - 1)),
+                                            si.n_points(nd, 1, False)), **tuning)
     for _ in range(args.launches):
         plan.run(b0, b1)
     torch.cuda.synchronize()
@@ -627,6 +648,11 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--bt", type=int, default=0, help="force b_T for the headline run")
     ap.add_argument("--probe", action="store_true")
+    ap.add_argument("--probe3d", action="store_true",
+                    help="with --probe: the 7-point star at 512^3 (default plan) instead")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("DIR", "KERNEL"),
+                    help="print per-dispatch averages of every counter in a rocprofv3 --pmc "
+                         "output directory for kernels whose name contains KERNEL")
     ap.add_argument("--full-sweep3d", action="store_true",
                     help="time every compiled 3D variant at 512^3, T = 1000")
     ap.add_argument("--full-sweep", action="store_true",
@@ -647,6 +673,9 @@ def main(argv=None):
                     help="turn two rocprofv3 --pmc runs of --probe into the traffic record")
     ap.add_argument("--command", default="", help="command line recorded with --ingest-counters")
     args = ap.parse_args(argv)
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return 0
     if args.ingest_counters:
         ingest_counters(args.ingest_counters[0], args.ingest_counters[1], TRAFFIC_RECORD,
                         TRAFFIC_RECORD.replace(".json", ".md"), args.command)

@@ -57,7 +57,7 @@ s5d_status build_step(const std::vector<RoundItem>& items, std::vector<unsigned 
       // write through an aligned temporary: blob may reallocate below
       scratch.assign(static_cast<size_t>(item_bytes) + 16, 0);
       void* tmp = reinterpret_cast<void*>(align_up(reinterpret_cast<uintptr_t>(scratch.data()), 16));
-      nblk[j] = fill_round_item(ri.plan, ri.bt, ri.src, ri.dst, tmp);
+      nblk[j] = fill_round_item(ri.plan, ri.bt, ri.src, ri.dst, tmp, ri.chunk);
       if (nblk[j] <= 0) return fail(S5D_EUNSUPPORTED, "grid too large for one launch");
       std::memcpy(blob.data() + g.items_off + j * static_cast<size_t>(item_bytes), tmp,
                   static_cast<size_t>(item_bytes));
@@ -188,6 +188,24 @@ s5d_status s5d_batch_create(const s5d_plan* const* plans, void* const* buf0, voi
         b->boundaries.push_back(h);
       }
     }
+    // Each grid shares its launches with the grids of the same kernel
+    // variant: its stream blocks are chosen for its share of the machine (its
+    // fraction of that group's cell-updates), which gives the small grids
+    // fewer, longer blocks than they would take alone.  The block length does
+    // not change any result bit.
+    std::vector<int> chunks(static_cast<size_t>(n), 0);
+    std::map<s5d::LaunchBatchFn, double> group_work;
+    std::vector<double> work(static_cast<size_t>(n), 0.0);
+    std::vector<s5d::LaunchBatchFn> group(static_cast<size_t>(n), nullptr);
+    for (int32_t g = 0; g < n; ++g) {
+      if (rounds[g].empty()) continue;
+      work[g] = static_cast<double>(plans[g]->d.steps) * static_cast<double>(plans[g]->bytes / plans[g]->elem);
+      group[g] = s5d::batch_hooks(plans[g], plans[g]->tun.bt).launch;
+      group_work[group[g]] += work[g];
+    }
+    for (int32_t g = 0; g < n; ++g)
+      if (!rounds[g].empty() && group_work[group[g]] > 0)
+        chunks[g] = s5d::shared_chunk(plans[g], plans[g]->tun.bt, work[g] / group_work[group[g]]);
     std::vector<unsigned char> blob;
     b->steps.resize(kmax);
     for (size_t k = 0; k < kmax; ++k) {
@@ -195,7 +213,7 @@ s5d_status s5d_batch_create(const s5d_plan* const* plans, void* const* buf0, voi
       for (int32_t g = 0; g < n; ++g) {
         if (k >= rounds[g].size()) continue;
         void* bufs[2] = {buf0[g], buf1[g]};
-        items.push_back(s5d::RoundItem{plans[g], rounds[g][k], bufs[k % 2], bufs[(k + 1) % 2]});
+        items.push_back(s5d::RoundItem{plans[g], rounds[g][k], bufs[k % 2], bufs[(k + 1) % 2], chunks[g]});
       }
       const s5d_status st = s5d::build_step(items, blob, b->steps[k]);
       if (st != S5D_OK) {

@@ -18,6 +18,7 @@ struct RoundItem {
   int bt;
   const void* src;
   void* dst;
+  int chunk;  // stream-block length for this launch (0: the plan's)
 };
 
 // One batched launch: the kernel variant, and the byte offsets of its items

@@ -21,6 +21,7 @@ struct s5d_plan {
   int elem;
   int kind;                  // kernel kind: KIND_F32, KIND_F64 or KIND_F32_COMP
   bool direct = false;       // direct kernels (one step per launch) instead of blocked ones
+  bool chunk_auto = false;   // stream_chunk was chosen by the library (not asked for)
   s5d::Kernel2D by_bt[16];   // 2D: index bt -> kernel for a round of bt steps (same tile)
   s5d::Kernel3D by_bt3[16];  // 3D: likewise
   // device copy of the coefficients in the working type (direct kernels);
@@ -50,7 +51,13 @@ struct BatchHooks {
 };
 BatchHooks batch_hooks(const s5d_plan* p, int bt);
 // Write p's batch item for a round into `item`; returns its workgroups.
-int fill_round_item(const s5d_plan* p, int bt, const void* src, void* dst, void* item);
+int fill_round_item(const s5d_plan* p, int bt, const void* src, void* dst, void* item, int chunk = 0);
+
+// Stream-block length for a grid that shares each launch with others and
+// gets about `share` (0 < share <= 1) of the machine's workgroup slots: the
+// library's chooser run for that many slots.  The plan's own length when the
+// caller chose it, or for direct kernels.
+int shared_chunk(const s5d_plan* p, int bt, double share);
 
 // Copy the fixed boundary of buf0 into buf1 (before the first round).
 hipError_t launch_boundary_copy(const s5d_plan* p, const void* buf0, void* buf1, hipStream_t stream);

@@ -52,16 +52,20 @@ struct Round2D {
 };
 
 // Stream blocks of a 2D launch, laid out for the XCDs.  Workgroups are
-// dispatched round-robin over the kXcds XCDs, so workgroup b runs on XCD
-// b % kXcds; that XCD takes band b % kXcds of the rows (hb = ceil(I0 / kXcds)
-// rows) and walks its workgroups in the order b / kXcds.  A band is cut into
-// n1 blocks of h1 rows followed by n2 blocks of h2 rows (h2 = h1 / 2 when
-// h1 >= 32, the last block possibly shorter): each XCD runs its long blocks
-// first and ends on short ones, which shortens the tail of the launch, and
-// neighbouring tiles of a block row run on one XCD and share its L2.
+// dispatched round-robin over the kXcds XCDs.  The rows are cut into nb bands
+// (nb = 8, or fewer when a band would not hold one block of h_SN rows: 4, 2,
+// 1) of hb = ceil(I0 / nb) rows; workgroup b works on band b % nb, so with
+// nb = 8 band x runs on XCD x, and walks its blocks in the order b / nb.  A
+// band is cut into n1 blocks of h1 rows followed by n2 blocks of h2 rows: when
+// the band holds more than two blocks of h1 rows, its last rows go in blocks
+// of h2 = h1 / 2 (h1 >= 32), so each XCD runs its long blocks first and ends
+// on short ones, which shortens the tail of the launch; otherwise every block
+// is h1 rows (h2 = h1, the last one possibly shorter).  Neighbouring tiles of
+// a block row run on one XCD and share its L2.
 constexpr int kXcds = 8;
 
 struct Bands2D {
+  int32_t nb;      // bands
   int32_t hb;      // rows per band
   int32_t h1, n1;  // long blocks: rows, count
   int32_t h2, n2;  // short blocks: rows, count
@@ -69,12 +73,20 @@ struct Bands2D {
 
 __host__ __device__ inline Bands2D make_bands2d(int I0, int chunk) {
   Bands2D g;
-  g.hb = (I0 + kXcds - 1) / kXcds;
-  g.h1 = chunk < 1 ? 1 : (chunk < g.hb ? chunk : g.hb);
+  const int h = chunk < 1 ? 1 : chunk;
+  g.nb = kXcds;
+  while (g.nb > 1 && (I0 + g.nb - 1) / g.nb < h) g.nb /= 2;
+  g.hb = (I0 + g.nb - 1) / g.nb;
+  g.h1 = h < g.hb ? h : g.hb;
   if (g.h1 < 1) g.h1 = 1;
-  g.h2 = g.h1 >= 32 ? g.h1 / 2 : g.h1;
   const int nfull = g.hb / g.h1;
-  g.n1 = nfull > 2 ? nfull - 2 : 0;
+  if (nfull > 2 && g.h1 >= 32) {
+    g.n1 = nfull - 2;
+    g.h2 = g.h1 / 2;
+  } else {
+    g.n1 = 0;
+    g.h2 = g.h1;
+  }
   g.n2 = (g.hb - g.n1 * g.h1 + g.h2 - 1) / g.h2;
   return g;
 }
@@ -101,7 +113,6 @@ struct Sweep2DArgs {
   int32_t ntiles;   // tiles across axis 1
   int32_t nwaves;   // waves per band: ntiles * (n1 + n2)
   Bands2D g;        // stream blocks (h_SN = g.h1)
-  int32_t pad;
 };
 
 using Launch2DFn = hipError_t (*)(const Round2D&);

@@ -347,7 +347,7 @@ s5d_status s5d_server_tick(s5d_server* s, int32_t* n_running, int32_t* n_queued)
       items.reserve(s->running.size());
       for (Request* r : s->running) {
         const size_t k = r->next++;
-        items.push_back(s5d::RoundItem{&r->plan, r->rounds[k], r->buf[k % 2], r->buf[(k + 1) % 2]});
+        items.push_back(s5d::RoundItem{&r->plan, r->rounds[k], r->buf[k % 2], r->buf[(k + 1) % 2], 0});
       }
       steps.emplace_back();
       st = s5d::build_step(items, blob, steps.back());

@@ -282,7 +282,8 @@ __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPac
 }
 
 // Workgroup lb of one grid's launch: kWavesPerBlock waves, one tile each, of
-// band lb % kXcds (the XCD the workgroup runs on in a launch of its own).
+// band lb % nb (with 8 bands, the XCD the workgroup runs on in a launch of
+// its own).
 template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
 __device__ __forceinline__ void sweep2d_block(const Sweep2DArgs& a, const CoefPack<T, npts(2, R, BOX)>& cf, int lb,
                                               EdgeStash<T, R, BT, CPL>* stash) {
@@ -292,8 +293,9 @@ __device__ __forceinline__ void sweep2d_block(const Sweep2DArgs& a, const CoefPa
   static_assert(R <= CPL, "the lane exchange reaches one neighbouring lane only");
   static_assert(C >= 1, "tile narrower than its overlap");
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int x = lb % kXcds;
-  const int wid = (lb / kXcds) * kWavesPerBlock + wib;  // wave within the band
+  const int nb = a.g.nb;
+  const int x = lb % nb;
+  const int wid = (lb / nb) * kWavesPerBlock + wib;  // wave within the band
   if (wid >= a.nwaves) return;
   const int lane = threadIdx.x & 63;
   const int tile = wid % a.ntiles;
@@ -353,13 +355,12 @@ Sweep2DArgs make_args2d(const Round2D& rd, CoefPack<T, npts(2, R, BOX)>& cf) {
   a.ntiles = (rd.I1 + C - 1) / C;
   const int64_t nw = static_cast<int64_t>(a.ntiles) * (a.g.n1 + a.g.n2);
   a.nwaves = nw > INT32_MAX / kXcds ? 0 : static_cast<int32_t>(nw);
-  a.pad = 0;
   return a;
 }
 
-// Workgroups of a launch: kXcds bands of ceil(nwaves / kWavesPerBlock).
+// Workgroups of a launch: nb bands of ceil(nwaves / kWavesPerBlock).
 inline int blocks2d(const Sweep2DArgs& a) {
-  return kXcds * ((a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock);
+  return a.g.nb * ((a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock);
 }
 
 template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>

@@ -103,7 +103,7 @@ RoundModel model_round2d(const s5d_plan* p, int bt) {
   }
   double rows_read = 0, rows_comp = 0;
   int64_t blocks = 0;  // non-empty stream blocks
-  for (int x = 0; x < kXcds; ++x)
+  for (int x = 0; x < g.nb; ++x)
     for (int c = 0; c < g.n1 + g.n2; ++c) {
       int a = 0, b = 0;
       band_rows2d(g, r, static_cast<int>(I0), x, c, a, b);

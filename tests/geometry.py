@@ -24,16 +24,24 @@ def compute_width(w, bt, r, elem):
 
 
 def stream_blocks_2d(I0, r, chunk, xcds=8):
-    """Output-row ranges [a, b) of a 2D launch's stream blocks: 8 bands of
-    ceil(I0 / 8) rows (one per XCD); a band holds blocks of h = min(chunk,
-    band) rows, and when it has room for more than two, its last rows go in
-    blocks of h // 2 rows (h >= 32) so each XCD ends on short blocks."""
-    hb = -(-I0 // xcds)
-    h1 = max(1, min(chunk, hb))
-    h2 = h1 // 2 if h1 >= 32 else h1
-    n1 = max(0, hb // h1 - 2)
+    """Output-row ranges [a, b) of a 2D launch's stream blocks.  The rows form
+    nb bands of ceil(I0 / nb) rows, nb = 8 or the largest of 4, 2, 1 whose
+    bands still hold one block of h_SN rows.  A band holds blocks of
+    h = min(chunk, band) rows; when it has room for more than two of them
+    (and h >= 32), its last rows go in blocks of h // 2, so each XCD ends on
+    short blocks."""
+    h = max(1, chunk)
+    nb = xcds
+    while nb > 1 and -(-I0 // nb) < h:
+        nb //= 2
+    hb = -(-I0 // nb)
+    h1 = max(1, min(h, hb))
+    if hb // h1 > 2 and h1 >= 32:
+        n1, h2 = hb // h1 - 2, h1 // 2
+    else:
+        n1, h2 = 0, h1
     out = []
-    for x in range(xcds):
+    for x in range(nb):
         lo, hi = r + x * hb, min(r + (x + 1) * hb, I0 + r)
         a = lo
         for _ in range(n1):

@@ -1,6 +1,6 @@
-"""GPU parity of the 2D stream-block layout: one band of ceil(I0/8) rows per
-XCD, long blocks of h_SN rows first and a tail of h_SN/2-row blocks last,
-ragged bands and ragged last blocks.
+"""GPU parity of the 2D stream-block layout: bands of rows (one per XCD, or
+fewer when a band would not hold one block), long blocks of h_SN rows first
+and a tail of h_SN/2-row blocks last, ragged bands and ragged last blocks.
 
 Bars: every stream-block length gives the same bits (the method's result does
 not depend on the blocking); the compensated kernels equal the compensated
@@ -20,7 +20,7 @@ from gpu_util import rel_errors, run_gpu, say
 pytestmark = pytest.mark.gpu
 
 INTERIOR = (8 * 150 + 37, 300)   # bands of 155 rows, the last one 122
-CHUNKS = (32, 40, 155, 7, 64)
+CHUNKS = (32, 40, 155, 7, 64, 400, 1237)  # 400: two bands; 1237: one band
 STEPS = 23
 
 
