@@ -318,14 +318,16 @@ s5d_status plan_2d(s5d_plan* p, const s5d_tuning& req, int box, int r) {
     p->by_bt[b] = e->make();
   }
   int chunk = req.stream_chunk;
-  if (chunk == 0) {
+  {
     const DeviceInfo dev = query_device();
     int occ = dev.ok ? p->by_bt[bt].occupancy() : 0;
     if (occ <= 0) occ = 2;
+    p->slots = static_cast<int64_t>(dev.cus) * occ * s5d::kWavesPerBlock;
+  }
+  if (chunk == 0) {
     const int64_t C = s5d::compute_width(64 * cpl, bt, r, p->elem);
     const int64_t ntiles = (d.interior[1] + C - 1) / C;
-    const int64_t slots = static_cast<int64_t>(dev.cus) * occ * s5d::kWavesPerBlock;
-    chunk = choose_chunk(d.interior[0], ntiles, slots, bt, r);
+    chunk = choose_chunk(d.interior[0], ntiles, p->slots, bt, r);
     p->chunk_auto = true;
   }
   if (chunk < 1) return fail(S5D_EINVAL, "stream_chunk must be >= 1");
@@ -458,14 +460,11 @@ int fill_round_item(const s5d_plan* p, int bt, const void* src, void* dst, void*
 }
 
 int shared_chunk(const s5d_plan* p, int bt, double share) {
-  if (p->direct || !p->chunk_auto || p->d.ndim != 2 || bt < 1) return p->tun.stream_chunk;
-  const DeviceInfo dev = query_device();
-  int occ = dev.ok && p->by_bt[bt].occupancy ? p->by_bt[bt].occupancy() : 0;
-  if (occ <= 0) occ = 2;
+  if (p->direct || !p->chunk_auto || p->d.ndim != 2 || bt < 1 || p->slots <= 0) return p->tun.stream_chunk;
   const int r = p->d.radius;
   const int64_t C = s5d::compute_width(64 * p->tun.cells_per_lane, bt, r, p->elem);
   const int64_t ntiles = (p->d.interior[1] + C - 1) / C;
-  const double all = static_cast<double>(dev.cus) * occ * s5d::kWavesPerBlock;
+  const double all = static_cast<double>(p->slots);  // the plan's own variant (depth p->tun.bt)
   const int64_t slots = std::max<int64_t>(1, static_cast<int64_t>(all * std::min(1.0, std::max(share, 0.0))));
   return choose_chunk(p->d.interior[0], ntiles, slots, bt, r);
 }
@@ -581,6 +580,7 @@ s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_p
     }
     p->direct = false;
     p->chunk_auto = false;
+    p->slots = 0;
     p->dcoef.reset();
     std::memset(&p->tun, 0, sizeof(p->tun));
     p->tun.struct_size = sizeof(s5d_tuning);

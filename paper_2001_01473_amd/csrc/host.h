@@ -22,6 +22,7 @@ struct s5d_plan {
   int kind;                  // kernel kind: KIND_F32, KIND_F64 or KIND_F32_COMP
   bool direct = false;       // direct kernels (one step per launch) instead of blocked ones
   bool chunk_auto = false;   // stream_chunk was chosen by the library (not asked for)
+  int64_t slots = 0;         // 2D: resident waves of the plan's variant on the whole device
   s5d::Kernel2D by_bt[16];   // 2D: index bt -> kernel for a round of bt steps (same tile)
   s5d::Kernel3D by_bt3[16];  // 3D: likewise
   // device copy of the coefficients in the working type (direct kernels);

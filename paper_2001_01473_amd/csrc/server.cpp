@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -49,6 +50,8 @@ struct Request {
   int64_t bytes2 = 0;  // both buffers
   int64_t updates = 0;
 };
+
+double cells_of(const Request* r) { return static_cast<double>(r->plan.bytes / r->plan.elem); }
 
 struct Slot {
   unsigned char* host = nullptr;  // pinned staging
@@ -343,11 +346,22 @@ s5d_status s5d_server_tick(s5d_server* s, int32_t* n_running, int32_t* n_queued)
     std::vector<std::vector<s5d::GroupLaunch>> steps;
     std::vector<std::vector<Request*>> fin_after;  // requests whose last round is in step j
     for (int j = 0; j < K && !s->running.empty(); ++j) {
+      // as in a batch: each request's stream blocks are chosen for its share
+      // of the launch it joins (its fraction of the step's cell-updates of its
+      // kernel variant); results do not depend on the block length
+      std::map<s5d::LaunchBatchFn, double> group_work;
+      for (Request* r : s->running) {
+        const int bt = r->rounds[r->next];
+        group_work[s5d::batch_hooks(&r->plan, bt).launch] += static_cast<double>(bt) * cells_of(r);
+      }
       std::vector<s5d::RoundItem> items;
       items.reserve(s->running.size());
       for (Request* r : s->running) {
         const size_t k = r->next++;
-        items.push_back(s5d::RoundItem{&r->plan, r->rounds[k], r->buf[k % 2], r->buf[(k + 1) % 2], 0});
+        const int bt = r->rounds[k];
+        const double gw = group_work[s5d::batch_hooks(&r->plan, bt).launch];
+        const int chunk = gw > 0 ? s5d::shared_chunk(&r->plan, bt, bt * cells_of(r) / gw) : 0;
+        items.push_back(s5d::RoundItem{&r->plan, bt, r->buf[k % 2], r->buf[(k + 1) % 2], chunk});
       }
       steps.emplace_back();
       st = s5d::build_step(items, blob, steps.back());
