@@ -104,13 +104,16 @@ typedef struct s5d_tuning {
 
 /* Kernel families (s5d_tuning.kernel). */
 #define S5D_KERNEL_AUTO 0    /* temporally blocked where compiled, else direct; direct
-                                also for a 2D plain-accumulation star or box of
-                                radius <= 2 whose tuning asks for bt = 1 and nothing
-                                else (faster than blocking at depth 1) */
+                                also where it measured faster: a plain-accumulation
+                                2D star or box of radius <= 2, or 3D 7-point star,
+                                whose tuning asks for bt = 1 and nothing else; the
+                                compensated 3D stars of radius <= 2; the float32
+                                125-point and compensated 27-point boxes */
 #define S5D_KERNEL_BLOCKED 1 /* b_T fused steps per launch (AN5D "Execution Model") */
 #define S5D_KERNEL_DIRECT 2  /* one step per launch, every radius 1..4 and shape: 2D stars
-                                and boxes of radius <= 2 stream whole rows, the others
-                                work from an LDS-staged tile (the plan's bt is 1) */
+                                and boxes of radius <= 2 and 3D stars stream whole
+                                rows, the others work from an LDS-staged tile (the
+                                plan's bt is 1) */
 
 typedef struct s5d_plan s5d_plan; /* opaque; immutable once created */
 

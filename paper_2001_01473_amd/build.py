@@ -43,7 +43,7 @@ DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
 
 HOST_SOURCES = ["abi.cpp", "batch.cpp", "server.cpp", "tune.cpp", "halo.hip", "norms.hip", "direct.hip"]
 HEADERS = ["s5d_internal.h", "kcommon.h", "sweep2d.h", "sweep3d.h"]
-HOST_HEADERS = ["host.h", "batch.h", "norms.h", "direct.h", "stream2d.h"]  # not included by the variant units
+HOST_HEADERS = ["host.h", "batch.h", "norms.h", "direct.h", "stream2d.h", "stream3d.h"]  # not included by the variant units
 
 # Kernel kinds: (name, C++ type, 32-bit words per element, accumulation
 # policy).  Kind 2 is float32 with compensated (Dot2) accumulation.

@@ -85,9 +85,13 @@ Default3D default_tuning3(int kind, int box, int r) {
 int default_bt3(int kind, int box, int r) { return default_tuning3(kind, box, r).bt; }
 
 // Stencils whose direct kernel measured faster than every blocked variant
-// on MI355X at 512^3 (the 125-point float32 box; the compensated 27-point box).
+// on MI355X at 512^3: the 125-point float32 box, the compensated 27-point
+// box, and the compensated stars (row streaming: 473 vs 433 GCell/s for the
+// 7-point star, 276 vs 194 for the 13-point one).
 bool prefer_direct(int kind, int ndim, int box, int r) {
-  return ndim == 3 && box && ((kind == KIND_F32 && r == 2) || (kind == KIND_F32_COMP && r == 1));
+  if (ndim != 3) return false;
+  if (!box) return kind == KIND_F32_COMP && r <= 2;
+  return (kind == KIND_F32 && r == 2) || (kind == KIND_F32_COMP && r == 1);
 }
 
 // Is any blocked variant compiled for this stencil?
@@ -599,11 +603,12 @@ s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_p
   }
   const bool no_blocking = req.bt <= 1 && req.cells_per_lane == 0 && req.rows_per_wave == 0 && req.tile0 == 0 &&
                            req.tile1 == 0 && req.stream_chunk == 0;
-  // b_T = 1 asked for a 2D stencil: the row-streaming direct kernel (plain
-  // accumulation; stars and boxes of radius <= 2) is faster than the blocked
-  // kernel at depth 1
-  const bool stream_bt1 = req.kernel == S5D_KERNEL_AUTO && no_blocking && req.bt == 1 && d.ndim == 2 &&
-                          p->kind != KIND_F32_COMP && (!box || r <= 2);
+  // b_T = 1 asked for: the row-streaming direct kernel (plain accumulation;
+  // 2D stars and boxes of radius <= 2, the 3D 7-point star) is faster than
+  // the blocked kernel at depth 1
+  const bool stream_bt1 = req.kernel == S5D_KERNEL_AUTO && no_blocking && req.bt == 1 &&
+                          p->kind != KIND_F32_COMP &&
+                          ((d.ndim == 2 && (!box || r <= 2)) || (d.ndim == 3 && !box && r == 1));
   if (st != S5D_OK) {
     if (req.kernel == S5D_KERNEL_DIRECT || stream_bt1 ||
         (req.kernel == S5D_KERNEL_AUTO && no_blocking && req.bt == 0 && prefer_direct(p->kind, d.ndim, box, r))) {

@@ -2,13 +2,15 @@
 // kind, radius 1..4 and shape, in 2D and 3D.
 #include "direct.h"
 #include "stream2d.h"
+#include "stream3d.h"
 
 namespace s5d {
 namespace {
 
 // 2D: the row-streaming kernel (stream2d.h), except for box stencils of
 // radius 3 and 4, whose 2r+1 full-row reads per thread lose to the LDS-staged
-// tiles (measured on MI355X); 3D: the LDS-staged tiles.
+// tiles (measured on MI355X); 3D: the row-streaming kernel (stream3d.h) for
+// star stencils, the LDS-staged tiles for box stencils.
 template <typename T, int ACC, int R, bool BOX>
 Kernel2D make2d() {
   if constexpr (BOX && R >= 3)
@@ -33,15 +35,26 @@ Kernel2D make2d() {
 
 template <typename T, int ACC, int R, bool BOX>
 Kernel3D make3d() {
-  return Kernel3D{&launch_direct3d<T, ACC, R, BOX>,
-                  &occupancy_direct<T, ACC, 3, R, BOX>,
-                  0,
-                  kDirectY3,
-                  1,
-                  1,
-                  &fill_direct3d<R>,
-                  &launch_direct_batch<T, ACC, 3, R, BOX>,
-                  static_cast<int>(sizeof(DirectArgs))};
+  if constexpr (!BOX)
+    return Kernel3D{&launch_stream3d<T, ACC, R, BOX>,
+                    &occupancy_stream3d<T, ACC, R, BOX>,
+                    0,
+                    1,
+                    kStream3DThreads / 64,
+                    1,
+                    &fill_stream3d<T>,
+                    &launch_stream3d_batch<T, ACC, R, BOX>,
+                    static_cast<int>(sizeof(Stream3DArgs))};
+  else
+    return Kernel3D{&launch_direct3d<T, ACC, R, BOX>,
+                    &occupancy_direct<T, ACC, 3, R, BOX>,
+                    0,
+                    kDirectY3,
+                    1,
+                    1,
+                    &fill_direct3d<R>,
+                    &launch_direct_batch<T, ACC, 3, R, BOX>,
+                    static_cast<int>(sizeof(DirectArgs))};
 }
 
 template <typename T, int ACC>

@@ -1,0 +1,234 @@
+// Direct 3D kernel: one time step per launch, streaming whole rows.
+//
+// Every wave64 computes one segment of 64 x CPL cells (one 16-byte vector per
+// lane) of one interior row (plane p, row i) of the axis-2 extent; waves are
+// numbered segment-fastest, then row, then plane, and workgroups run in plain
+// dispatch order, so at any moment the machine streams one window of
+// consecutive rows and the rows a cell shares with its neighbours are re-read
+// from the caches.  For each stencil row (p + d0, i + d1) a lane loads its
+// vector straight from global memory, with the r neighbours on either side
+// where the row needs them: the centre row of a star takes them from the
+// adjacent lanes (DPP; the wave's edge lanes from two wave-uniform loads),
+// box rows load them per lane.  Each cell sums its terms in the canonical
+// (d0, d1, d2) order with the same accumulation policy as the blocked kernels,
+// so the results have the same bits.  Stores are non-temporal.  No LDS, no
+// barrier: waves are independent.
+#pragma once
+
+#include "kcommon.h"
+
+namespace s5d {
+
+struct Stream3DArgs {
+  const void* src;
+  void* dst;
+  const void* coef;  // device array of the coefficients, canonical order, working type
+  int32_t I0, I1, I2;
+  int32_t nws;       // wave segments per row
+  int64_t nwaves;    // I0 * I1 * nws
+};
+
+constexpr int kStream3DThreads = 512;
+
+template <typename T, int ACC, int R, bool BOX>
+__device__ __forceinline__ void stream3d_wave(const Stream3DArgs& a, int64_t gw) {
+  constexpr int CPL = 16 / static_cast<int>(sizeof(T));
+  constexpr int E = 2 * R + 1;
+  constexpr bool DPPH = !BOX && R <= CPL;  // a lane shift reaches one neighbouring lane only
+  const int P1 = a.I1 + 2 * R, P2 = a.I2 + 2 * R;
+  const int ws = static_cast<int>(gw % a.nws);
+  const int64_t row = gw / a.nws;
+  const int i = R + static_cast<int>(row % a.I1);  // interior row
+  const int p = R + static_cast<int>(row / a.I1);  // interior plane
+  const int lane = threadIdx.x & 63;
+  const int wc0 = R + ws * 64 * CPL;  // first column of this wave (uniform)
+  const int c0 = wc0 + lane * CPL;    // first column of this lane
+  const T* __restrict__ src = static_cast<const T*>(a.src);
+  T* __restrict__ dst = static_cast<T*>(a.dst);
+  const T* __restrict__ c = static_cast<const T*>(a.coef);
+
+  // the lane's cells of row (pp, ii) and, if `full`, their r neighbours on
+  // each side; columns beyond the padded row read 0 (they feed no stored cell)
+  auto load_row = [&](T (&x)[CPL + 2 * R], int pp, int ii, bool full) S5D_INL {
+    const T* rp = src + (static_cast<int64_t>(pp) * P1 + ii) * P2;
+    if (DPPH || !full) {
+      if (c0 + CPL <= P2) {
+        const LaneVec<T, CPL> v = *reinterpret_cast<const LaneVec<T, CPL>*>(rp + c0);
+        sfor<CPL>([&](auto K) S5D_INL { x[R + K] = v.v[K]; });
+      } else {
+        sfor<CPL>([&](auto K) S5D_INL { x[R + K] = c0 + K < P2 ? rp[c0 + K] : T(0); });
+      }
+      if (full) {
+        sfor<R>([&](auto J) S5D_INL {
+          x[J] = lane_from_lower(x[CPL + J]);
+          x[R + CPL + J] = lane_from_upper(x[R + J]);
+        });
+        sfor<R>([&](auto J) S5D_INL {
+          const int lc = wc0 - R + J, rc = wc0 + 64 * CPL + J;
+          const T lft = rp[lc < P2 ? lc : P2 - 1];
+          const T rgt = rp[rc < P2 ? rc : P2 - 1];
+          x[J] = lane == 0 ? lft : x[J];
+          x[R + CPL + J] = lane == 63 ? (rc < P2 ? rgt : T(0)) : x[R + CPL + J];
+        });
+      }
+    } else if (c0 + CPL + R <= P2) {
+      const LaneVec<T, CPL> v = *reinterpret_cast<const LaneVec<T, CPL>*>(rp + c0);
+      sfor<CPL>([&](auto K) S5D_INL { x[R + K] = v.v[K]; });
+      sfor<R>([&](auto J) S5D_INL {
+        x[J] = rp[c0 - R + J];
+        x[R + CPL + J] = rp[c0 + CPL + J];
+      });
+    } else {
+      sfor<CPL + 2 * R>([&](auto X) S5D_INL {
+        const int col = c0 - R + X;
+        x[X] = col < P2 ? rp[col] : T(0);
+      });
+    }
+  };
+
+  Accum<T, ACC> acc[CPL];
+  if constexpr (BOX) {
+    sfor<E>([&](auto D0) S5D_INL {
+      sfor<E>([&](auto D1) S5D_INL {
+        T x[CPL + 2 * R];
+        load_row(x, p + D0 - R, i + D1 - R, true);
+        sfor<E>([&](auto D2) S5D_INL {
+          const T ck = c[(D0 * E + D1) * E + D2];
+          sfor<CPL>([&](auto K) S5D_INL {
+            if constexpr (D0 == 0 && D1 == 0 && D2 == 0) acc[K].first(ck, x[K + D2]);
+            else acc[K].add(ck, x[K + D2]);
+          });
+        });
+      });
+    });
+  } else {
+    // (d0, 0, 0) for d0 < 0
+    sfor<R>([&](auto J) S5D_INL {
+      T x[CPL + 2 * R];
+      load_row(x, p - R + J, i, false);
+      const T ck = c[J];
+      sfor<CPL>([&](auto K) S5D_INL {
+        if constexpr (J == 0) acc[K].first(ck, x[R + K]);
+        else acc[K].add(ck, x[R + K]);
+      });
+    });
+    // (0, d1, 0) for d1 < 0
+    sfor<R>([&](auto J) S5D_INL {
+      T x[CPL + 2 * R];
+      load_row(x, p, i - R + J, false);
+      const T ck = c[R + J];
+      sfor<CPL>([&](auto K) S5D_INL { acc[K].add(ck, x[R + K]); });
+    });
+    // (0, 0, d2)
+    {
+      T x[CPL + 2 * R];
+      load_row(x, p, i, true);
+      sfor<E>([&](auto D2) S5D_INL {
+        const T ck = c[2 * R + D2];
+        sfor<CPL>([&](auto K) S5D_INL { acc[K].add(ck, x[K + D2]); });
+      });
+    }
+    // (0, d1, 0) for d1 > 0
+    sfor<R>([&](auto J) S5D_INL {
+      T x[CPL + 2 * R];
+      load_row(x, p, i + 1 + J, false);
+      const T ck = c[4 * R + 1 + J];
+      sfor<CPL>([&](auto K) S5D_INL { acc[K].add(ck, x[R + K]); });
+    });
+    // (d0, 0, 0) for d0 > 0
+    sfor<R>([&](auto J) S5D_INL {
+      T x[CPL + 2 * R];
+      load_row(x, p + 1 + J, i, false);
+      const T ck = c[5 * R + 1 + J];
+      sfor<CPL>([&](auto K) S5D_INL { acc[K].add(ck, x[R + K]); });
+    });
+  }
+
+  T out[CPL];
+  sfor<CPL>([&](auto K) S5D_INL { out[K] = acc[K].value(); });
+  T* wp = dst + (static_cast<int64_t>(p) * P1 + i) * P2;
+  if (c0 + CPL <= a.I2 + R) {
+    using VT = T __attribute__((ext_vector_type(CPL), aligned(sizeof(T))));  // element-aligned address
+    VT v;
+    sfor<CPL>([&](auto K) S5D_INL { v[+K] = out[K]; });
+    __builtin_nontemporal_store(v, reinterpret_cast<VT*>(wp + c0));
+  } else {
+    sfor<CPL>([&](auto K) S5D_INL {
+      if (c0 + K < a.I2 + R) wp[c0 + K] = out[K];
+    });
+  }
+}
+
+// Workgroup lb: waves lb * 8 .. lb * 8 + 7 of the grid (those past the last
+// one return at once).
+template <typename T, int ACC, int R, bool BOX>
+__device__ __forceinline__ void stream3d_block(const Stream3DArgs& a, int lb) {
+  const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+  const int64_t gw = static_cast<int64_t>(lb) * (kStream3DThreads / 64) + w;
+  if (gw >= a.nwaves) return;
+  stream3d_wave<T, ACC, R, BOX>(a, gw);
+}
+
+template <typename T, int ACC, int R, bool BOX>
+__global__ __launch_bounds__(kStream3DThreads) void stream3d_kernel(Stream3DArgs a) {
+  stream3d_block<T, ACC, R, BOX>(a, blockIdx.x);
+}
+
+template <typename T, int ACC, int R, bool BOX>
+__global__ __launch_bounds__(kStream3DThreads) void stream3d_batch_kernel(const Stream3DArgs* __restrict__ items,
+                                                                          const BlockMap* __restrict__ map) {
+  const BlockMap m = map[xcd_logical_block(blockIdx.x, gridDim.x)];
+  const Stream3DArgs a = uniform_copy(items[__builtin_amdgcn_readfirstlane(m.item)]);
+  stream3d_block<T, ACC, R, BOX>(a, __builtin_amdgcn_readfirstlane(m.block));
+}
+
+template <typename T>
+int64_t stream3d_args(Stream3DArgs& a, const Round3D& rd) {
+  constexpr int CPL = 16 / static_cast<int>(sizeof(T));
+  a.src = rd.src;
+  a.dst = rd.dst;
+  a.coef = rd.dcoef;
+  a.I0 = rd.I0;
+  a.I1 = rd.I1;
+  a.I2 = rd.I2;
+  a.nws = (rd.I2 + 64 * CPL - 1) / (64 * CPL);
+  a.nwaves = static_cast<int64_t>(rd.I0) * rd.I1 * a.nws;
+  const int64_t nblk = (a.nwaves + kStream3DThreads / 64 - 1) / (kStream3DThreads / 64);
+  return nblk > INT32_MAX ? 0 : nblk;
+}
+
+template <typename T, int ACC, int R, bool BOX>
+hipError_t launch_stream3d(const Round3D& rd) {
+  Stream3DArgs a;
+  const int64_t nblk = stream3d_args<T>(a, rd);
+  if (nblk == 0) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((stream3d_kernel<T, ACC, R, BOX>), dim3(static_cast<unsigned>(nblk)), dim3(kStream3DThreads), 0,
+                     rd.stream, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+int fill_stream3d(void* item, const Round3D& rd) {
+  Stream3DArgs a;
+  const int64_t nblk = stream3d_args<T>(a, rd);
+  __builtin_memcpy(item, &a, sizeof(a));
+  return static_cast<int>(nblk);
+}
+
+template <typename T, int ACC, int R, bool BOX>
+hipError_t launch_stream3d_batch(const void* items, const BlockMap* map, int nblocks, hipStream_t stream) {
+  hipLaunchKernelGGL((stream3d_batch_kernel<T, ACC, R, BOX>), dim3(nblocks), dim3(kStream3DThreads), 0, stream,
+                     static_cast<const Stream3DArgs*>(items), map);
+  return hipGetLastError();
+}
+
+template <typename T, int ACC, int R, bool BOX>
+int occupancy_stream3d() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stream3d_kernel<T, ACC, R, BOX>, kStream3DThreads, 0) !=
+      hipSuccess)
+    return 0;
+  return nb;
+}
+
+}  // namespace s5d

@@ -130,11 +130,13 @@ RoundModel model_round_direct(const s5d_plan* p) {
   double cells = 1, staged = 1;
   int64_t tiles = 1;
   // 2D: one row of 512 x (16 bytes / w) cells per workgroup, no LDS (box
-  // radius 3-4: LDS tiles of 16 x 64); 3D: LDS tiles of 4 x 8 x (64, or 32
-  // for r >= 3) cells
+  // radius 3-4: LDS tiles of 16 x 64); 3D stars: about 8 rows of 64 x (16
+  // bytes / w) cells per workgroup (one per wave), no LDS; 3D boxes: LDS
+  // tiles of 4 x 8 x (64, or 32 for r >= 3) cells
   const bool lds2 = p->d.shape == S5D_BOX && r >= 3;
+  const bool lds3 = p->d.shape == S5D_BOX;
   const int dims2[2] = {lds2 ? 16 : 1, lds2 ? 64 : 512 * 16 / static_cast<int>(w)};
-  const int dims3[3] = {4, 8, r >= 3 ? 32 : 64};
+  const int dims3[3] = {lds3 ? 4 : 1, lds3 ? 8 : 8, lds3 ? (r >= 3 ? 32 : 64) : 64 * 16 / static_cast<int>(w)};
   for (int a = 0; a < nd; ++a) {
     const int64_t I = p->d.interior[a];
     const int D = nd == 2 ? dims2[a] : dims3[a];
@@ -146,7 +148,7 @@ RoundModel model_round_direct(const s5d_plan* p) {
   const double n_terms = static_cast<double>(p->coeffs.size());
   m.gm = 2.0 * cells * w;
   const double ops_term = p->kind == KIND_F32_COMP ? 9.0 : 1.0;
-  const bool uses_lds = nd == 3 || lds2;
+  const bool uses_lds = (nd == 3 && lds3) || (nd == 2 && lds2);
   m.ops = cells * (n_terms * ops_term + 2.0) + (uses_lds ? static_cast<double>(tiles) * staged * 2.0 : 0.0);
   m.lds = uses_lds ? cells * n_terms * w + static_cast<double>(tiles) * staged * w : 0.0;
   m.wgs = tiles;

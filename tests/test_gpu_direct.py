@@ -124,3 +124,33 @@ def test_row_streaming_spans_segments(s, dt):
         if dt == np.float64:
             ref = oracle.sweep(g_in, radius=r, box=box, coeffs=c_in, steps=T)
             assert max(rel_errors(a, ref)) <= 1e-12
+
+
+@pytest.mark.parametrize("kind", ["f32", "f64", "f32c"])
+@pytest.mark.parametrize("r", [1, 2, 3])
+def test_row_streaming_3d_spans_segments(kind, r):
+    """The 3D row-streaming kernel (star stencils) on rows of several wave
+    segments (64 lanes x one 16-byte vector) plus a ragged tail, and on rows
+    shorter than one wave: the same bits as the blocked kernel at b_T = 1
+    (radius 1-2, where one is built), float64 within 1e-12 of the oracle,
+    compensated float32 bit-exact against the compensated oracle."""
+    dt = np.float64 if kind == "f64" else np.float32
+    accum = "compensated" if kind == "f32c" else "plain"
+    seg = 64 * (16 // np.dtype(dt).itemsize)
+    T = 2
+    for interior in ((5, 7, 2 * seg + 77), (4, 3, 19)):
+        case = si.make_case(97 + r, 3, r, False, interior, T)
+        c_in, g_in = case.as_dtype(dt)
+        say("3D row streaming", kind, "r", r, interior)
+        a, ia = run_gpu(g_in, radius=r, box=False, coeffs=case.coeffs, steps=T, accum=accum, kernel="direct")
+        assert ia["kernel"] == 2
+        if r <= 2:
+            b, ib = run_gpu(g_in, radius=r, box=False, coeffs=case.coeffs, steps=T, accum=accum,
+                            kernel="blocked", bt=1)
+            np.testing.assert_array_equal(a, b)
+        if kind == "f64":
+            ref = oracle.sweep(g_in, radius=r, box=False, coeffs=c_in, steps=T)
+            assert max(rel_errors(a, ref)) <= 1e-12
+        elif kind == "f32c":
+            want = oracle.sweep(g_in, radius=r, box=False, coeffs=c_in, steps=T, accum="compensated")
+            np.testing.assert_array_equal(a, want)
