@@ -82,11 +82,23 @@ s5d_status build_step(const std::vector<RoundItem>& items, std::vector<unsigned 
   return S5D_OK;
 }
 
-hipError_t enqueue_step(const std::vector<GroupLaunch>& launches, const unsigned char* dev, hipStream_t stream) {
-  for (const GroupLaunch& g : launches) {
-    const hipError_t e =
-        g.fn(dev + g.items_off, reinterpret_cast<const BlockMap*>(dev + g.map_off), g.nblocks, stream);
+hipError_t enqueue_step(const std::vector<GroupLaunch>& launches, const unsigned char* dev, hipStream_t stream,
+                        hipStream_t side, hipEvent_t fork, hipEvent_t join) {
+  const bool split = side && fork && join && launches.size() >= 2;
+  hipError_t e = hipSuccess;
+  if (split) {
+    if ((e = hipEventRecord(fork, stream)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(side, fork, 0)) != hipSuccess) return e;
+  }
+  for (size_t j = 0; j < launches.size(); ++j) {
+    const GroupLaunch& g = launches[j];
+    e = g.fn(dev + g.items_off, reinterpret_cast<const BlockMap*>(dev + g.map_off), g.nblocks,
+             split && j % 2 == 1 ? side : stream);
     if (e != hipSuccess) return e;
+  }
+  if (split) {
+    if ((e = hipEventRecord(join, side)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(stream, join, 0)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -113,6 +125,8 @@ struct s5d_batch {
   std::vector<int32_t> result_index;
   unsigned char* dev = nullptr;
   int device = 0;
+  hipStream_t side = nullptr;  // second stream for steps of several kernel variants
+  hipEvent_t fork = nullptr, join = nullptr;
   bool graph = false;
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -126,7 +140,7 @@ hipError_t enqueue_batch(const s5d_batch* b, hipStream_t st) {
     if (e != hipSuccess) return e;
   }
   for (const auto& step : b->steps) {
-    const hipError_t e = s5d::enqueue_step(step, b->dev, st);
+    const hipError_t e = s5d::enqueue_step(step, b->dev, st, b->side, b->fork, b->join);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -137,6 +151,9 @@ void release(s5d_batch* b) {
   if (b->exec || b->dev) (void)hipDeviceSynchronize();
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+  if (b->side) (void)hipStreamDestroy(b->side);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->join) (void)hipEventDestroy(b->join);
   if (b->dev) (void)hipFree(b->dev);
   (void)hipGetLastError();
   delete b;
@@ -188,24 +205,22 @@ s5d_status s5d_batch_create(const s5d_plan* const* plans, void* const* buf0, voi
         b->boundaries.push_back(h);
       }
     }
-    // Each grid shares its launches with the grids of the same kernel
-    // variant: its stream blocks are chosen for its share of the machine (its
-    // fraction of that group's cell-updates), which gives the small grids
-    // fewer, longer blocks than they would take alone.  The block length does
-    // not change any result bit.
+    // Each grid shares the machine with all the others (launches of different
+    // kernel variants overlap on two streams): its stream blocks are chosen
+    // for its fraction of the batch's cell-updates, which gives the small
+    // grids fewer, longer blocks than they would take alone.  The block
+    // length does not change any result bit.
     std::vector<int> chunks(static_cast<size_t>(n), 0);
-    std::map<s5d::LaunchBatchFn, double> group_work;
     std::vector<double> work(static_cast<size_t>(n), 0.0);
-    std::vector<s5d::LaunchBatchFn> group(static_cast<size_t>(n), nullptr);
+    double total_work = 0;
     for (int32_t g = 0; g < n; ++g) {
       if (rounds[g].empty()) continue;
       work[g] = static_cast<double>(plans[g]->d.steps) * static_cast<double>(plans[g]->bytes / plans[g]->elem);
-      group[g] = s5d::batch_hooks(plans[g], plans[g]->tun.bt).launch;
-      group_work[group[g]] += work[g];
+      total_work += work[g];
     }
     for (int32_t g = 0; g < n; ++g)
-      if (!rounds[g].empty() && group_work[group[g]] > 0)
-        chunks[g] = s5d::shared_chunk(plans[g], plans[g]->tun.bt, work[g] / group_work[group[g]]);
+      if (!rounds[g].empty() && total_work > 0)
+        chunks[g] = s5d::shared_chunk(plans[g], plans[g]->tun.bt, work[g] / total_work);
     std::vector<unsigned char> blob;
     b->steps.resize(kmax);
     for (size_t k = 0; k < kmax; ++k) {
@@ -236,6 +251,17 @@ s5d_status s5d_batch_create(const s5d_plan* const* plans, void* const* buf0, voi
       if (e != hipSuccess) {
         release(b);
         return device_fail(e, "upload of the batch tables");
+      }
+      bool multi = false;
+      for (const auto& step : b->steps) multi = multi || step.size() >= 2;
+      if (multi) {
+        e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+          release(b);
+          return device_fail(e, "side stream of the batch");
+        }
       }
     }
   } catch (const std::bad_alloc&) {

@@ -35,8 +35,13 @@ struct GroupLaunch {
 s5d_status build_step(const std::vector<RoundItem>& items, std::vector<unsigned char>& blob,
                       std::vector<GroupLaunch>& out);
 
-// Enqueue the launches of a step whose table was uploaded to `dev`.
-hipError_t enqueue_step(const std::vector<GroupLaunch>& launches, const unsigned char* dev, hipStream_t stream);
+// Enqueue the launches of a step whose table was uploaded to `dev`.  With a
+// side stream and two events, a step of several launches (kernel variants)
+// forks: every other launch goes to the side stream, so launches of different
+// variants overlap (they touch different grids), and the step joins back into
+// `stream` before the next one.
+hipError_t enqueue_step(const std::vector<GroupLaunch>& launches, const unsigned char* dev, hipStream_t stream,
+                        hipStream_t side = nullptr, hipEvent_t fork = nullptr, hipEvent_t join = nullptr);
 
 // EINVAL if any two [begin, end) byte ranges overlap.
 s5d_status check_disjoint(const std::vector<std::pair<uintptr_t, uintptr_t>>& ranges);

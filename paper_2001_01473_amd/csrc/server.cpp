@@ -71,6 +71,8 @@ struct Finishing {
 struct s5d_server {
   s5d_server_config cfg;
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;  // second stream: launches of different kernel variants overlap
+  hipEvent_t fork = nullptr, join = nullptr;
   hipEvent_t base = nullptr;
   std::chrono::steady_clock::time_point t0;
   std::unordered_map<int64_t, std::unique_ptr<Request>> reqs;
@@ -216,6 +218,10 @@ void destroy_server(s5d_server* s) {
   for (Finishing& f : s->finishing) (void)hipEventDestroy(f.ev);
   for (hipEvent_t ev : s->event_pool) (void)hipEventDestroy(ev);
   if (s->base) (void)hipEventDestroy(s->base);
+  if (s->side) (void)hipStreamSynchronize(s->side);
+  if (s->side) (void)hipStreamDestroy(s->side);
+  if (s->fork) (void)hipEventDestroy(s->fork);
+  if (s->join) (void)hipEventDestroy(s->join);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   (void)hipGetLastError();
   delete s;
@@ -252,6 +258,14 @@ s5d_status s5d_server_create(const s5d_server_config* config, s5d_server** out) 
     s->stream = nullptr;
     destroy_server(s);
     return device_fail(e, "server stream");
+  }
+  e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
+  if (e != hipSuccess) s->side = nullptr;
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    destroy_server(s);
+    return device_fail(e, "server side stream");
   }
   for (Slot& sl : s->slots) {
     e = hipEventCreate(&sl.ev);
@@ -347,20 +361,17 @@ s5d_status s5d_server_tick(s5d_server* s, int32_t* n_running, int32_t* n_queued)
     std::vector<std::vector<Request*>> fin_after;  // requests whose last round is in step j
     for (int j = 0; j < K && !s->running.empty(); ++j) {
       // as in a batch: each request's stream blocks are chosen for its share
-      // of the launch it joins (its fraction of the step's cell-updates of its
-      // kernel variant); results do not depend on the block length
-      std::map<s5d::LaunchBatchFn, double> group_work;
-      for (Request* r : s->running) {
-        const int bt = r->rounds[r->next];
-        group_work[s5d::batch_hooks(&r->plan, bt).launch] += static_cast<double>(bt) * cells_of(r);
-      }
+      // of the step (its fraction of the step's cell-updates; the launches of
+      // a step overlap on two streams); results do not depend on the block
+      // length
+      double step_work = 0;
+      for (Request* r : s->running) step_work += static_cast<double>(r->rounds[r->next]) * cells_of(r);
       std::vector<s5d::RoundItem> items;
       items.reserve(s->running.size());
       for (Request* r : s->running) {
         const size_t k = r->next++;
         const int bt = r->rounds[k];
-        const double gw = group_work[s5d::batch_hooks(&r->plan, bt).launch];
-        const int chunk = gw > 0 ? s5d::shared_chunk(&r->plan, bt, bt * cells_of(r) / gw) : 0;
+        const int chunk = step_work > 0 ? s5d::shared_chunk(&r->plan, bt, bt * cells_of(r) / step_work) : 0;
         items.push_back(s5d::RoundItem{&r->plan, bt, r->buf[k % 2], r->buf[(k + 1) % 2], chunk});
       }
       steps.emplace_back();
@@ -388,7 +399,7 @@ s5d_status s5d_server_tick(s5d_server* s, int32_t* n_running, int32_t* n_queued)
     hipError_t e = hipMemcpyAsync(sl.dev, sl.host, blob.size(), hipMemcpyHostToDevice, s->stream);
     if (e != hipSuccess) return device_fail(e, "tick table upload");
     for (size_t j = 0; j < steps.size(); ++j) {
-      e = s5d::enqueue_step(steps[j], sl.dev, s->stream);
+      e = s5d::enqueue_step(steps[j], sl.dev, s->stream, s->side, s->fork, s->join);
       if (e != hipSuccess) return device_fail(e, "tick launch");
       s->launches += static_cast<int64_t>(steps[j].size());
       if (!fin_after[j].empty()) {
