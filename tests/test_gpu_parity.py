@@ -202,3 +202,24 @@ def test_full_size_16384_sampled(dt, r, box):
     np.testing.assert_array_equal(got, base)
     del base, got
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_full_size_16384_streaming_bt1(dt):
+    """16384^2 interior at b_T = 1, the launch the benchmark's b_T = 1 point
+    times (the row-streaming kernel): the same bits as the blocked kernel at
+    b_T = 1, sampled cells against the windowed oracle."""
+    N, r, T = 16384, 1, 3
+    case = si.make_case(si.workload_seed(1), 2, r, False, (N, N), T)
+    c_in, g_in = case.as_dtype(dt)
+    say("full-size streaming b_T=1", dt.__name__)
+    got, info = run_gpu(g_in, radius=r, box=False, coeffs=case.coeffs, steps=T, bt=1)
+    assert info["kernel"] == 2
+    base, binfo = run_gpu(g_in, radius=r, box=False, coeffs=case.coeffs, steps=T, bt=1, kernel="blocked")
+    assert binfo["kernel"] == 1
+    np.testing.assert_array_equal(got, base)
+    P = N + 2 * r
+    rng = np.random.default_rng(9)
+    pts = [(r, r), (r, P - r - 1), (P - r - 1, r), (P - r - 1, P - r - 1), (P // 2, P // 2)]
+    pts += [(int(a), int(b)) for a, b in rng.integers(r, P - r, size=(11, 2))]
+    _crop_check(got, g_in, c_in.astype(np.float64), r, False, T, pts)
