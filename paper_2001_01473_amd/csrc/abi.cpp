@@ -139,9 +139,9 @@ Default2D default_tuning(int kind, int box, int r) {
   static const Default2D f32_star[4] = {{10, 4}, {7, 4}, {5, 4}, {3, 4}};
   static const Default2D f32_box[2] = {{7, 4}, {3, 4}};
   static const Default2D f64_star[4] = {{10, 2}, {6, 2}, {3, 4}, {2, 4}};
-  static const Default2D f64_box[2] = {{8, 2}, {4, 2}};
-  static const Default2D comp_star[4] = {{3, 4}, {1, 4}, {1, 4}, {1, 4}};
-  static const Default2D comp_box[2] = {{1, 4}, {1, 4}};
+  static const Default2D f64_box[2] = {{9, 2}, {4, 2}};
+  static const Default2D comp_star[4] = {{3, 4}, {3, 4}, {1, 4}, {1, 4}};
+  static const Default2D comp_box[2] = {{3, 4}, {1, 4}};
   if (kind == KIND_F32) return box ? f32_box[r - 1] : f32_star[r - 1];
   if (kind == KIND_F32_COMP) return box ? comp_box[r - 1] : comp_star[r - 1];
   return box ? f64_box[r - 1] : f64_star[r - 1];
