@@ -68,10 +68,13 @@ const Entry3D* find3d(int kind, int box, int r, int cpl, int m, int nw, int bt) 
 }
 
 // 3D defaults: depth and rows per wave (tile family), the best pair measured
-// on MI355X at 512^3, T = 1000.  Compensated accumulation is bound by
-// arithmetic from the first level on.
+// on MI355X at 512^3, T = 1000, and a floor on the stream-block length where
+// the measured optimum lies above the chooser's pick (the float32 27-point
+// box: 64 planes, 620 GCell/s against 566 at the chooser's 19).  Compensated
+// accumulation is bound by arithmetic from the first level on.
 struct Default3D {
   int bt, m;
+  int hmin = 0;  // stream-block floor (planes), for extents of at least 4 * hmin
 };
 Default3D default_tuning3(int kind, int box, int r) {
   if (kind == KIND_F32_COMP) return {1, 2};
@@ -79,7 +82,7 @@ Default3D default_tuning3(int kind, int box, int r) {
     if (r == 1) return box ? Default3D{2, 4} : Default3D{3, 2};
     return box ? Default3D{1, 2} : Default3D{2, 2};
   }
-  if (r == 1) return box ? Default3D{2, 4} : Default3D{3, 4};
+  if (r == 1) return box ? Default3D{2, 4, 64} : Default3D{3, 4};
   return box ? Default3D{1, 4} : Default3D{2, 4};
 }
 int default_bt3(int kind, int box, int r) { return default_tuning3(kind, box, r).bt; }
@@ -390,6 +393,9 @@ s5d_status plan_3d(s5d_plan* p, const s5d_tuning& req, int box, int r) {
     const int64_t ntiles = ((d.interior[1] + C1 - 1) / C1) * ((d.interior[2] + C2 - 1) / C2);
     const int64_t slots = static_cast<int64_t>(dev.cus) * occ;  // resident workgroups
     chunk = choose_chunk(d.interior[0], ntiles, slots, bt, r);
+    const Default3D def = default_tuning3(p->kind, box, r);
+    if (def.hmin > 0 && bt == def.bt && fam->m == def.m && d.interior[0] >= 4LL * def.hmin)
+      chunk = std::max(chunk, def.hmin);
   }
   if (chunk < 1) return fail(S5D_EINVAL, "stream_chunk must be >= 1");
   p->tun.bt = bt;
