@@ -669,6 +669,9 @@ def main(argv=None):
     ap.add_argument("--serve-budgets-gib", default="64")
     ap.add_argument("--only-extras", action="store_true",
                     help="skip the headline sweep; print only the --batch/--serve records")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="leave the batched, serving (32 requests) and accuracy records out of "
+                         "the default run")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs of --probe into the traffic record")
     ap.add_argument("--command", default="", help="command line recorded with --ingest-counters")
@@ -762,12 +765,25 @@ def main(argv=None):
                 s = time_steps(p, 1, 1)
                 g = N * N * T_STEPS / s / 1e9
                 curve.append({"dtype": dtype, "bt": bt, "cells_per_lane": p.info["cells_per_lane"],
-                              "stream_chunk": p.info["stream_chunk"], "gcells": g})
+                              "stream_chunk": p.info["stream_chunk"],
+                              "kernel": ("auto", "blocked", "direct")[p.info["kernel"]], "gcells": g,
+                              "pct_of_bt_hbm_roofline": 100.0 * g * 2 * (4 if dtype == "f32" else 8) /
+                              HBM_PEAK_GBS / bt})
                 p.close()
                 print("bt-curve star2d1r %s bt=%d: %.1f GCell/s" % (dtype, bt, g),
                       file=sys.stderr, flush=True)
         rec["bt_curve_star2d1r"] = curve
         rec["sweep3d_512"] = sweep3d_default()
+    if not args.no_extras:
+        # the metric's batched/served-vs-plain and p50/p99 parts, at their
+        # default (short) sizes; --batch / --serve / --accuracy alone give
+        # the larger runs recorded under profiles/
+        if "batched" not in extras:
+            extras["batched"] = bench_batch()
+        if "serving" not in extras:
+            extras["serving"] = bench_serve()
+        if "accuracy" not in extras:
+            extras["accuracy"] = bench_accuracy()
     rec.update(extras)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(1, False, "f32")
