@@ -177,7 +177,8 @@ def roofline(r, box, dtype, bt, tuning):
             rec = json.load(f)
         if rec.get("kernel_hash") == kernel_source_hash() and rec.get("bt") == bt:
             traffic = rec.get("hbm_bytes_per_launch")
-    common = {"kernel": "sweep2d %s r=%d %s bt=%d" % ("box" if box else "star", r, dtype, bt),
+    family = "stream2d" if info.get("kernel") == 2 else "sweep2d"  # direct row streaming at b_T = 1
+    common = {"kernel": "%s %s r=%d %s bt=%d" % (family, "box" if box else "star", r, dtype, bt),
               "alu_unpacked": {"peak": ALU_PEAK_UNPACKED_TFLOPS, "unit": "TFLOP/s",
                                "frac": alu / ALU_PEAK_UNPACKED_TFLOPS},
               "launch_ms": dt * 1e3, "traffic": traffic,
