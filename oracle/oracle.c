@@ -189,6 +189,164 @@ int oracle_sweep_f32_dot2(int ndim, int radius, int box, const int64_t *interior
     return (int)(steps % 2);
 }
 
+/*
+ * Expression stencils of the paper's general benchmarks (Table 3,
+ * "Benchmarks"), each written as its plain definition in the working
+ * precision, product then add, no fused multiply-add.
+ *
+ * DIV: the weighted sum of a star or box stencil, divided by one constant c0
+ *   A[(t+1)%2][p] = (sum_k c_k * A[t%2][p + o_k]) / c0
+ * (j2d5pt: 2D star radius 1, printed in Fig. 4 with divisor 118; j2d9pt: 2D
+ * star radius 2; j2d9pt-gol: 2D box radius 1; j3d27pt: 3D box radius 1).
+ * The sum is formed left to right in canonical offset order, then divided
+ * once.
+ */
+#define ORACLE_SWEEP_DIV(NAME, REAL)                                              \
+    int NAME(int ndim, int radius, int box, const int64_t *interior,              \
+             int64_t steps, const REAL *coeffs, int64_t n_coeffs, REAL c0,        \
+             REAL *buf0, REAL *buf1, int threads)                                 \
+    {                                                                             \
+        int32_t off3[3 * ORACLE_MAX_POINTS];                                      \
+        int n = oracle_offsets(ndim, radius, box, off3);                          \
+        if (n < 0 || n != n_coeffs || steps < 0 || !buf0 || !buf1 || !coeffs)     \
+            return -1;                                                            \
+        int64_t I0 = interior[0], I1 = interior[1];                               \
+        int64_t I2 = (ndim == 3) ? interior[2] : 1;                               \
+        if (I0 < 1 || I1 < 1 || I2 < 1)                                           \
+            return -1;                                                            \
+        int64_t r = radius;                                                       \
+        int64_t P0 = I0 + 2 * r, P1 = I1 + 2 * r;                                 \
+        int64_t P2 = (ndim == 3) ? I2 + 2 * r : 1;                                \
+        int64_t r2 = (ndim == 3) ? r : 0;                                         \
+        int64_t lin[ORACLE_MAX_POINTS];                                           \
+        for (int k = 0; k < n; ++k)                                               \
+            lin[k] = (int64_t)off3[3 * k] * P1 * P2 +                             \
+                     (int64_t)off3[3 * k + 1] * P2 + (int64_t)off3[3 * k + 2];    \
+        memcpy(buf1, buf0, (size_t)(P0 * P1 * P2) * sizeof(REAL));               \
+        if (threads > 0) {                                                        \
+            OMP_SET(threads);                                                     \
+        }                                                                         \
+        for (int64_t t = 0; t < steps; ++t) {                                     \
+            const REAL *src = (t % 2 == 0) ? buf0 : buf1;                         \
+            REAL *dst = (t % 2 == 0) ? buf1 : buf0;                               \
+            OMP_FOR                                                               \
+            for (int64_t i0 = r; i0 < r + I0; ++i0)                               \
+                for (int64_t i1 = r; i1 < r + I1; ++i1)                           \
+                    for (int64_t i2 = r2; i2 < r2 + I2; ++i2) {                   \
+                        int64_t p = (i0 * P1 + i1) * P2 + i2;                     \
+                        REAL acc = coeffs[0] * src[p + lin[0]];                   \
+                        for (int k = 1; k < n; ++k)                               \
+                            acc = acc + coeffs[k] * src[p + lin[k]];              \
+                        dst[p] = acc / c0;                                        \
+                    }                                                             \
+        }                                                                         \
+        return (int)(steps % 2);                                                  \
+    }
+
+ORACLE_SWEEP_DIV(oracle_sweep_div_f64, double)
+ORACLE_SWEEP_DIV(oracle_sweep_div_f32, float)
+
+/*
+ * gradient2d (Table 3): 2D, radius 1, non-linear in the cell values:
+ *   A'[p] = cc * A[p] + 1 / sqrt(c0 + sum_n (A[p] - A[n]) * (A[p] - A[n]))
+ * over the four axis neighbours n of p.  The sum starts from c0 and adds the
+ * squared differences in canonical offset order, (-1,0), (0,-1), (0,1),
+ * (1,0); then the square root (correctly rounded), the quotient 1 / root and
+ * finally the product cc * A[p] plus that quotient.
+ */
+#define ORACLE_SWEEP_GRADIENT(NAME, REAL, SQRT)                                   \
+    int NAME(const int64_t *interior, int64_t steps, REAL cc, REAL c0,            \
+             REAL *buf0, REAL *buf1, int threads)                                 \
+    {                                                                             \
+        if (steps < 0 || !buf0 || !buf1)                                          \
+            return -1;                                                            \
+        int64_t I0 = interior[0], I1 = interior[1];                               \
+        if (I0 < 1 || I1 < 1)                                                     \
+            return -1;                                                            \
+        int64_t P0 = I0 + 2, P1 = I1 + 2;                                         \
+        const int64_t nb[4] = {-P1, -1, 1, P1};                                   \
+        memcpy(buf1, buf0, (size_t)(P0 * P1) * sizeof(REAL));                     \
+        if (threads > 0) {                                                        \
+            OMP_SET(threads);                                                     \
+        }                                                                         \
+        for (int64_t t = 0; t < steps; ++t) {                                     \
+            const REAL *src = (t % 2 == 0) ? buf0 : buf1;                         \
+            REAL *dst = (t % 2 == 0) ? buf1 : buf0;                               \
+            OMP_FOR                                                               \
+            for (int64_t i0 = 1; i0 < 1 + I0; ++i0)                               \
+                for (int64_t i1 = 1; i1 < 1 + I1; ++i1) {                         \
+                    int64_t p = i0 * P1 + i1;                                     \
+                    REAL s = c0;                                                  \
+                    for (int k = 0; k < 4; ++k) {                                 \
+                        REAL d = src[p] - src[p + nb[k]];                         \
+                        s = s + d * d;                                            \
+                    }                                                             \
+                    REAL root = SQRT(s);                                          \
+                    REAL q = (REAL)1 / root;                                      \
+                    dst[p] = cc * src[p] + q;                                     \
+                }                                                                 \
+        }                                                                         \
+        return (int)(steps % 2);                                                  \
+    }
+
+ORACLE_SWEEP_GRADIENT(oracle_sweep_gradient_f64, double, sqrt)
+ORACLE_SWEEP_GRADIENT(oracle_sweep_gradient_f32, float, sqrtf)
+
+/*
+ * Variable coefficients (multi-array input): every interior cell has its own
+ * weights,
+ *   A'[p] = sum_k C[k][p] * A[p + o_k]
+ * in canonical offset order.  C holds n_points arrays of the interior's
+ * extents (I0 x I1 [x I2], C order), weight k of all cells first: C[k][q] is
+ * weight k of the interior cell with 0-based interior index q.
+ */
+#define ORACLE_SWEEP_VARCOEF(NAME, REAL)                                          \
+    int NAME(int ndim, int radius, int box, const int64_t *interior,              \
+             int64_t steps, const REAL *cfield, REAL *buf0, REAL *buf1,           \
+             int threads)                                                         \
+    {                                                                             \
+        int32_t off3[3 * ORACLE_MAX_POINTS];                                      \
+        int n = oracle_offsets(ndim, radius, box, off3);                          \
+        if (n < 0 || steps < 0 || !buf0 || !buf1 || !cfield)                      \
+            return -1;                                                            \
+        int64_t I0 = interior[0], I1 = interior[1];                               \
+        int64_t I2 = (ndim == 3) ? interior[2] : 1;                               \
+        if (I0 < 1 || I1 < 1 || I2 < 1)                                           \
+            return -1;                                                            \
+        int64_t r = radius;                                                       \
+        int64_t P0 = I0 + 2 * r, P1 = I1 + 2 * r;                                 \
+        int64_t P2 = (ndim == 3) ? I2 + 2 * r : 1;                                \
+        int64_t r2 = (ndim == 3) ? r : 0;                                         \
+        int64_t cells = I0 * I1 * I2;                                             \
+        int64_t lin[ORACLE_MAX_POINTS];                                           \
+        for (int k = 0; k < n; ++k)                                               \
+            lin[k] = (int64_t)off3[3 * k] * P1 * P2 +                             \
+                     (int64_t)off3[3 * k + 1] * P2 + (int64_t)off3[3 * k + 2];    \
+        memcpy(buf1, buf0, (size_t)(P0 * P1 * P2) * sizeof(REAL));               \
+        if (threads > 0) {                                                        \
+            OMP_SET(threads);                                                     \
+        }                                                                         \
+        for (int64_t t = 0; t < steps; ++t) {                                     \
+            const REAL *src = (t % 2 == 0) ? buf0 : buf1;                         \
+            REAL *dst = (t % 2 == 0) ? buf1 : buf0;                               \
+            OMP_FOR                                                               \
+            for (int64_t i0 = r; i0 < r + I0; ++i0)                               \
+                for (int64_t i1 = r; i1 < r + I1; ++i1)                           \
+                    for (int64_t i2 = r2; i2 < r2 + I2; ++i2) {                   \
+                        int64_t p = (i0 * P1 + i1) * P2 + i2;                     \
+                        int64_t q = ((i0 - r) * I1 + (i1 - r)) * I2 + (i2 - r2);  \
+                        REAL acc = cfield[q] * src[p + lin[0]];                   \
+                        for (int k = 1; k < n; ++k)                               \
+                            acc = acc + cfield[k * cells + q] * src[p + lin[k]];  \
+                        dst[p] = acc;                                             \
+                    }                                                             \
+        }                                                                         \
+        return (int)(steps % 2);                                                  \
+    }
+
+ORACLE_SWEEP_VARCOEF(oracle_sweep_varcoef_f64, double)
+ORACLE_SWEEP_VARCOEF(oracle_sweep_varcoef_f32, float)
+
 /* Number of OpenMP threads a parallel region would use (1 without OpenMP). */
 int oracle_max_threads(void)
 {

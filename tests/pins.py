@@ -315,6 +315,24 @@ def load_fig4():
     return coeff, div, resp
 
 
+def load_fig4_pair():
+    """The second worked example of the Fig. 4 golden file: the displacement
+    of the cell that sums two non-zero products, and the two offsets whose
+    weights it adds (in the program's order) before dividing."""
+    path = os.path.join(GOLDEN, "fig4_j2d5pt_impulse.txt")
+    with open(path) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line.startswith("pair"):
+                key, _, val = line.partition("=")
+                at = tuple(int(v) for v in key[len("pair"):].strip(" ()").split(","))
+                terms = val.split("/")[0].strip(" ()").split("+")
+                offs = [tuple(int(v) for v in t.strip()[len("coeff"):].strip("()").split(","))
+                        for t in terms]
+                return at, offs
+    raise ValueError("no pair line in the Fig. 4 golden file")
+
+
 def check_fig4_impulse(sweep):
     coeff, div, resp = load_fig4()
     offs = canon_offsets(2, 1, False)
