@@ -197,26 +197,101 @@ def roofline(r, box, dtype, bt, tuning):
 
 
 def cpu_baseline(r, box, dtype, target_s=12.0):
-    """The CPU oracle on a bounded sample: the full grid for a few steps."""
+    """The CPU oracle on a bounded sample: the full grid for a few steps, on
+    all the threads OpenMP gives the process (os.cpu_count() unless
+    OMP_NUM_THREADS says otherwise)."""
     import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
     rng = np.random.default_rng(si.workload_seed(1))
     c = si.random_coeffs(rng, npts(r, box))
     g = rng.random(si.padded_shape((N, N), r)).astype(np.float32 if dtype == "f32" else np.float64)
-    oracle.sweep(g, radius=r, box=box, coeffs=c, steps=1)  # warm-up: first touch of the pages
+    oracle.sweep(g, radius=r, box=box, coeffs=c, steps=1, threads=threads)  # warm-up: first touch of the pages
     # grow the sample until one run takes at least target_s (each call also
     # copies the grid into its own two buffers, as the oracle always does)
     steps = 8
     while True:
         t0 = time.perf_counter()
-        oracle.sweep(g, radius=r, box=box, coeffs=c, steps=steps)
+        oracle.sweep(g, radius=r, box=box, coeffs=c, steps=steps, threads=threads)
         dt = time.perf_counter() - t0
         if dt >= target_s or steps >= T_STEPS:
             break
         steps = min(T_STEPS, int(steps * 1.15 * target_s / max(dt, 1e-3)) + 1)
+    cpu = _host_cpu()
     return {"value": N * N * steps / dt / 1e9, "unit": "GCell-updates/s",
-            "cores": oracle.max_threads(), "kind": "oracle",
+            "cores": threads, "nproc": cpu["nproc"], "cpu_model": cpu["cpu_model"], "kind": "oracle",
             "sample": "%s %s %dx%d interior, %d steps (of %d), %.1f s" % (
                 stencil_name(r, box), dtype, N, N, steps, T_STEPS, dt)}
+
+
+def bench_plain512(reps=20):
+    """The 512^2 float64 5-point star, T = 100, as a plain sweep (b_T = 1, one
+    launch per step; a 4 MB grid stays in the caches, so launch latency
+    dominates): eager launches and the same sweep replayed from a HIP graph
+    (checked to give the eager bits), beside the oracle on 1 thread and on all
+    threads (full grid, same steps)."""
+    import torch
+    import oracle
+    n, T = 512, 100
+    rng = np.random.default_rng(si.workload_seed(0))
+    c = si.random_coeffs(rng, 5)
+    g = si.random_grid(rng, si.padded_shape((n, n), 1))
+    p = Problem(1, False, "f64", steps=T, interior=(n, n), bt=1)
+    p.init.copy_(torch.from_numpy(g))
+    p.plan.close()
+    import paper_2001_01473_amd as s5d
+    p.plan = s5d.Plan(ndim=2, radius=1, box=False, dtype="f64", interior=(n, n), steps=T, coeffs=c, bt=1)
+    eager = time_steps(p, reps, 2)
+    p.reset()
+    idx = p.run()
+    torch.cuda.synchronize()
+    want = (p.buf0 if idx == 0 else p.buf1).clone()
+    # capture the whole sweep (boundary copy + 100 launches) into a graph
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    p.reset()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=side):
+        p.plan.run(p.buf0, p.buf1, stream=side)
+    for _ in range(3):
+        p.reset()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        if not torch.equal((p.buf0 if idx == 0 else p.buf1), want):
+            raise AssertionError("graph replay of the 512^2 sweep differs from the eager run")
+    total = 0.0
+    for _ in range(reps):
+        p.reset()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        graph.replay()
+        b.record()
+        b.synchronize()
+        total += a.elapsed_time(b) / 1e3
+    graphed = total / reps
+    n_all = oracle.max_threads()  # before the 1-thread run below changes OpenMP's default
+    want_host = oracle.sweep(g, radius=1, box=False, coeffs=c, steps=T, threads=n_all)
+    got = want.cpu().numpy()
+    from oracle import norms as onorms
+    nm = onorms.error_norms(got, want_host)
+    t1 = time.perf_counter()
+    oracle.sweep(g, radius=1, box=False, coeffs=c, steps=T, threads=1)
+    one = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    oracle.sweep(g, radius=1, box=False, coeffs=c, steps=T, threads=n_all)
+    allc = time.perf_counter() - t1
+    p.close()
+    upd = n * n * T
+    cpu = _host_cpu()
+    return {"workload": "star2d1r 512x512 f64 T=100, plain sweep (b_T = 1)",
+            "eager_gcells": upd / eager / 1e9, "graph_gcells": upd / graphed / 1e9,
+            "eager_ms": eager * 1e3, "graph_ms": graphed * 1e3,
+            "vs_oracle_normwise": float(nm[0] / nm[1]), "vs_oracle_elementwise": float(nm[2]),
+            "oracle_1thread_gcells": upd / one / 1e9, "oracle_all_gcells": upd / allc / 1e9,
+            "oracle_threads": n_all, "nproc": cpu["nproc"], "cpu_model": cpu["cpu_model"]}
 
 
 N3 = 512
@@ -226,7 +301,7 @@ def full_sweep3d():
     """Every compiled 3D variant at 512^3, T = 1000 (one warm-up, one timed run)."""
     import torch
     from paper_2001_01473_amd import build as lib_build
-    for kind, box, r, cpl, m, nw, bt, nr in lib_build.variants_3d():
+    for kind, box, r, cpl, m, nw, bt, nr in lib_build.linear_variants_3d():
         dtype, accum = KINDS[kind]
         name = "%s3d%dr" % ("box" if box else "star", r)
         try:
@@ -288,7 +363,7 @@ def full_sweep():
     """Every compiled 2D variant at 16384^2, T = 1000 (one warm-up, one timed run)."""
     import torch
     from paper_2001_01473_amd import build as lib_build
-    for kind, box, r, cpl, bt, nr in lib_build.variants_2d():
+    for kind, box, r, cpl, bt, nr in lib_build.linear_variants_2d():
         dtype, accum = KINDS[kind]
         try:
             p = Problem(r, bool(box), dtype, bt=bt, cells_per_lane=cpl, accum=accum)
@@ -304,6 +379,80 @@ def full_sweep():
               flush=True)
         p.close()
         torch.cuda.empty_cache()
+
+
+# The general benchmarks of AN5D Table 3 (FLOP per cell as printed there) and
+# the variable-coefficient stencils.  V100 "Tuned" GCell/s of Table 5 (its
+# GFLOP/s divided by the FLOP count) are context for the reader, not targets.
+EXPR_CASES = [
+    # name, ndim, radius, box, expr, FLOP/cell, V100 f32, V100 f64 GCell/s
+    ("j2d5pt", 2, 1, False, "div", 10, 616.0, 125.8),
+    ("j2d9pt", 2, 2, False, "div", 18, 355.4, 153.9),
+    ("j2d9pt-gol", 2, 1, True, "div", 18, 381.4, 77.4),
+    ("gradient2d", 2, 1, False, "gradient", 19, 419.2, 123.3),
+    ("j3d27pt", 3, 1, True, "div", 54, 115.8, 36.2),
+    ("varcoef2d1r", 2, 1, False, "varcoef", 9, None, None),
+    ("varcoef2d2r", 2, 2, False, "varcoef", 17, None, None),
+    ("varcoefbox2d1r", 2, 1, True, "varcoef", 17, None, None),
+]
+
+
+def sweep_expr(dtypes=("f32", "f64")):
+    """The expression stencils at the paper's sizes (16384^2, 512^3), T = 1000,
+    default plans.  Algorithmic bytes: 2w per cell per launch, plus n*w for
+    the per-cell weights (read once per launch)."""
+    import torch
+    import paper_2001_01473_amd as s5d
+    out = []
+    for name, nd, r, box, expr, flop, v100_32, v100_64 in EXPR_CASES:
+        for dtype in dtypes:
+            interior = (N3,) * 3 if nd == 3 else (N, N)
+            rng = np.random.default_rng(si.workload_seed(1 if nd == 2 else 2))
+            n = si.n_points(nd, r, box)
+            if expr == "div":
+                u = rng.random(n)
+                coeffs = list(u) + [float(u.sum())]
+            elif expr == "gradient":
+                coeffs = [0.3, 1.5]
+            else:
+                coeffs = None
+            td = torch.float32 if dtype == "f32" else torch.float64
+            shape = si.padded_shape(interior, r)
+            gen = torch.Generator(device="cuda:0").manual_seed(si.workload_seed(1))
+            x = torch.rand(shape, dtype=td, device="cuda:0", generator=gen)
+            y = torch.empty_like(x)
+            init = x.clone()
+            fields = None
+            if expr == "varcoef":
+                fields = torch.rand((n,) + interior, dtype=td, device="cuda:0", generator=gen)
+                fields /= fields.sum(dim=0, keepdim=True)
+            plan = s5d.Plan(ndim=nd, radius=r, box=box, dtype=dtype, interior=interior, steps=T_STEPS,
+                            coeffs=coeffs, expr=expr)
+            info = plan.query()
+            secs = []
+            for rep in range(2):
+                x.copy_(init)
+                torch.cuda.synchronize()
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                plan.run(x, y, fields=fields)
+                b.record()
+                b.synchronize()
+                secs.append(a.elapsed_time(b) / 1e3)
+            sec = secs[-1]
+            cells = float(np.prod(interior))
+            g = cells * T_STEPS / sec / 1e9
+            w = 4 if dtype == "f32" else 8
+            rec = {"stencil": name, "dtype": dtype, "bt": info["bt"], "gcells": g,
+                   "gflops_table3": g * flop, "pct_hbm_bound": 100.0 * g * 2 * w / HBM_PEAK_GBS,
+                   "v100_tuned_gcells": v100_32 if dtype == "f32" else v100_64}
+            out.append(rec)
+            print("expr %s %s bt=%d: %.1f GCell/s" % (name, dtype, info["bt"], g), file=sys.stderr, flush=True)
+            plan.close()
+            del x, y, init, fields
+            torch.cuda.empty_cache()
+    return out
 
 
 def _device_grid(shape, dtype, seed):
@@ -396,23 +545,29 @@ def bench_batch(reps=2):
     return out
 
 
-def bench_serve(n_requests=32, loads=(0.8,), budgets=(64 << 30,)):
-    """Serving mix: Poisson arrivals of mixed 2D/3D, star/box, r in {1,2},
-    float32/float64 requests with 10..1000 steps.  First the closed-loop
+def bench_serve(n_requests=32, loads=(0.5, 0.9), budgets=(64 << 30,)):
+    """Serving mix: Poisson arrivals of mixed 2D/3D, star/box, r in {1,2}
+    requests with 10..1000 steps, float32/float64 50/50 as drawn ("mixed"),
+    and the same requests all in float32 ("f32").  For each: the closed-loop
     capacity (all requests queued at once), then open-loop runs at the given
-    fractions of that capacity; p50/p99 latency = completion - arrival."""
+    fractions of that capacity; p50/p99 latency = completion - arrival.  The
+    plain baselines run the same requests one at a time with s5d_run: in
+    their own dtypes, and all in float64 (the plain per-grid float64 path)."""
     import torch
     import paper_2001_01473_amd as s5d
     base = si.serve_mix(si.workload_seed(4), n_requests, rate_per_s=1.0)
-    plans = [_plan_for(s, s["dtype"]) for s in base]
-    inits = [_device_grid(si.padded_shape(s["interior"], s["radius"]), s["dtype"], s["seed"])
-             for s in base]
     updates = [int(np.prod(s["interior"])) * s["steps"] for s in base]
     out = {"workload": "%d requests: 50%% 2D U{512..8192}^2 / 50%% 3D U{64..256}^3, star/box, "
                        "r in {1,2}, f32/f64, T U{10..1000}" % n_requests,
-           "updates": sum(updates)}
+           "updates": sum(updates), "streams": 4}
 
-    def serve(arrivals, budget):
+    def make(dtype_of):
+        plans = [_plan_for(s, dtype_of(s)) for s in base]
+        inits = [_device_grid(si.padded_shape(s["interior"], s["radius"]), dtype_of(s), s["seed"])
+                 for s in base]
+        return plans, inits
+
+    def serve(plans, inits, arrivals, budget):
         srv = s5d.Server(hbm_budget_bytes=budget)
         t0 = srv.now()
         order = sorted(range(len(plans)), key=lambda i: arrivals[i])
@@ -441,102 +596,189 @@ def bench_serve(n_requests=32, loads=(0.8,), budgets=(64 << 30,)):
         srv.close()
         return st
 
-    # plain: every request alone, one after the other
-    t = time.perf_counter()
-    for j, (p, x) in enumerate(zip(plans, inits)):
-        y = torch.empty_like(x)
-        p.run(x.clone(), y)
-        torch.cuda.synchronize()
-        print("plain: request %d done" % j, file=sys.stderr, flush=True)
-    plain = time.perf_counter() - t
-    out["plain_sequential_gcells"] = sum(updates) / plain / 1e9
-    cap = serve([0.0] * len(plans), budgets[0])
-    capacity = cap["updates_done"] / cap["makespan"]
-    out["capacity_gcells"] = capacity / 1e9
-    out["capacity_p50_s"], out["capacity_p99_s"] = cap["latency_p50"], cap["latency_p99"]
-    print("serve capacity %.1f GCell/s, plain %.1f GCell/s" % (capacity / 1e9,
-                                                                 out["plain_sequential_gcells"]),
-          file=sys.stderr, flush=True)
+    def one_by_one(plans, inits, label):
+        t = time.perf_counter()
+        for p, x in zip(plans, inits):
+            y = torch.empty_like(x)
+            p.run(x.clone(), y)
+            torch.cuda.synchronize()
+        sec = time.perf_counter() - t
+        print("plain %s one by one: %.1f GCell/s" % (label, sum(updates) / sec / 1e9), file=sys.stderr,
+              flush=True)
+        return sum(updates) / sec / 1e9
+
     mean_upd = float(np.mean(updates))
-    points = []
-    for budget in budgets:
-        for load in loads:
-            rate = load * capacity / mean_upd
-            arrivals = [s["arrival"] / rate for s in base]  # unit-rate arrivals rescaled
-            st = serve(arrivals, budget)
-            points.append({"offered_load": load, "budget_gib": budget / (1 << 30),
-                           "rate_per_s": rate, "throughput_gcells": st["updates_done"] /
-                           st["makespan"] / 1e9, "p50_s": st["latency_p50"],
-                           "p99_s": st["latency_p99"], "ticks": st["ticks"],
-                           "launches": st["launches"], "peak_gib": st["bytes_peak"] / (1 << 30)})
-            print("serve load %.2f budget %.0f GiB: p50 %.3f s p99 %.3f s, %.1f GCell/s" % (
-                load, budget / (1 << 30), st["latency_p50"], st["latency_p99"],
-                points[-1]["throughput_gcells"]), file=sys.stderr, flush=True)
-    out["points"] = points
+    plans64, inits64 = make(lambda s: "f64")
+    out["plain_f64_one_by_one_gcells"] = one_by_one(plans64, inits64, "f64")
+    for p in plans64:
+        p.close()
+    del inits64
+    for label, dtype_of in (("mixed", lambda s: s["dtype"]), ("f32", lambda s: "f32")):
+        plans, inits = make(dtype_of)
+        rec = {"plain_one_by_one_gcells": one_by_one(plans, inits, label)}
+        cap = serve(plans, inits, [0.0] * len(plans), budgets[0])
+        capacity = cap["updates_done"] / cap["makespan"]
+        rec.update(capacity_gcells=capacity / 1e9, capacity_p50_s=cap["latency_p50"],
+                   capacity_p99_s=cap["latency_p99"])
+        print("serve %s capacity %.1f GCell/s" % (label, capacity / 1e9), file=sys.stderr, flush=True)
+        points = []
+        for budget in budgets:
+            for load in loads:
+                rate = load * capacity / mean_upd
+                arrivals = [s["arrival"] / rate for s in base]  # unit-rate arrivals rescaled
+                st = serve(plans, inits, arrivals, budget)
+                points.append({"offered_load": load, "budget_gib": budget / (1 << 30),
+                               "rate_per_s": rate, "throughput_gcells": st["updates_done"] /
+                               st["makespan"] / 1e9, "p50_s": st["latency_p50"],
+                               "p99_s": st["latency_p99"], "ticks": st["ticks"],
+                               "launches": st["launches"], "peak_gib": st["bytes_peak"] / (1 << 30),
+                               "failed": st["failed"]})
+                print("serve %s load %.2f budget %.0f GiB: p50 %.3f s p99 %.3f s, %.1f GCell/s" % (
+                    label, load, budget / (1 << 30), st["latency_p50"], st["latency_p99"],
+                    points[-1]["throughput_gcells"]), file=sys.stderr, flush=True)
+        rec["points"] = points
+        out[label] = rec
+        for p in plans:
+            p.close()
+        del inits
+        torch.cuda.empty_cache()
+    out["f32_capacity_vs_plain_f64"] = out["f32"]["capacity_gcells"] / out["plain_f64_one_by_one_gcells"]
     return out
 
 
 def bench_accuracy():
-    """Error after T steps of float32 (plain and compensated accumulation)
-    against float64, all three started from the same float32-rounded grid and
-    coefficients and run on the GPU; the norms are the library's float64
-    reductions.  The float64 result is tied to the CPU oracle on sampled 2D
-    cells (the oracle run on the window of the initial grid that a cell's T-step
-    result depends on).  Workloads: 512^3 star3d1r and box3d1r, 16384^2
-    star2d1r, T = 1000."""
+    """Error after T = 1000 steps of float64, float32 and compensated float32
+    against the CPU oracle over every cell, at sizes the oracle finishes in
+    seconds: star2d1r at 2048^2, star3d1r and box3d1r at 128^3 (the same
+    comparison at the benchmark sizes is `--accuracy-full`)."""
+    rows = accuracy_full("all", None, n2=2048, n3=128, stencils2d=[(1, False)])
+    for row in rows:
+        print("accuracy %s %s: normwise %.3g, max abs %.3g (bar %.3g)" % (
+            row["stencil"], row["kind"], row["normwise"], row["max_abs_err"], row["bound"]),
+            file=sys.stderr, flush=True)
+    return rows
+
+
+def _host_cpu():
+    """Threads the oracle uses, the host's logical CPU count and its model name."""
+    import oracle
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cores": oracle.max_threads(), "nproc": os.cpu_count(), "cpu_model": model}
+
+
+def _accuracy_row(name, kind, got, ref, steps, n, max_a0, bound_kind):
+    """Error of a whole GPU grid against the whole oracle grid (numpy norms)."""
+    from oracle import norms as onorms
+    nm = onorms.error_norms(got, ref)
+    u32 = 2.0 ** -24
+    gamma = n * u32 / (1 - n * u32)
+    if bound_kind == "f64":
+        bound, ok = 1e-12, nm[0] / nm[1] <= 1e-12 and nm[2] <= 1e-12
+    elif bound_kind == "plain":
+        bound = steps * (gamma + u32) * max_a0
+        ok = nm[0] <= bound
+    else:
+        bound = steps * (u32 + gamma * gamma) * max_a0
+        ok = nm[0] <= bound
+    return {"stencil": name, "kind": kind, "max_abs_err": float(nm[0]), "normwise": float(nm[0] / nm[1]),
+            "elementwise": float(nm[2]), "rms_err": float(nm[3]), "bound": float(bound),
+            "bound_on": "normwise and elementwise relative" if bound_kind == "f64" else "max abs",
+            "ok": bool(ok)}
+
+
+def accuracy_full(which="all", md=None, n2=N, n3=N3, stencils2d=STENCILS):
+    """Whole-grid comparison with the CPU oracle at the benchmark sizes and
+    T = 1000: the six 2D stencils at 16384^2 and the 7-point star and 27-point
+    box at 512^3.  Float64 runs on float64 inputs against the oracle on the same
+    inputs (bar: normwise and elementwise relative error <= 1e-12); float32 and
+    compensated float32 on float32-rounded grid and coefficients against the
+    float64 oracle run on those rounded inputs (bars: T*(gamma_n + u)*max|A0|
+    plain, T*(u + gamma_n^2)*max|A0| compensated).  Every cell is compared."""
     import torch
     import oracle
     import paper_2001_01473_amd as s5d
-    out = []
-    for ndim, r, box, interior in ((3, 1, False, (N3, N3, N3)), (3, 1, True, (N3, N3, N3)),
-                                   (2, 1, False, (N, N))):
-        rng = np.random.default_rng(si.workload_seed(2 if ndim == 3 else 1))
-        c32 = si.random_coeffs(rng, si.n_points(ndim, r, box)).astype(np.float32)
-        c = c32.astype(np.float64)
-        shape = si.padded_shape(interior, r)
-        g32 = _device_grid(shape, "f32", si.workload_seed(5))
-        results = {}
-        for kind, dt, accum in (("f64", torch.float64, "plain"), ("f32", torch.float32, "plain"),
-                                ("f32c", torch.float32, "compensated")):
-            x = g32.to(dt, copy=True)  # each run starts from its own copy of the grid
-            y = torch.empty_like(x)
-            p = s5d.Plan(ndim=ndim, radius=r, box=box, dtype="f64" if kind == "f64" else "f32",
-                         interior=interior, steps=T_STEPS, coeffs=c, accum=accum)
-            idx = p.run(x, y)
-            torch.cuda.synchronize()
-            p.close()
-            results[kind] = x if idx == 0 else y
-            del x, y
-        assert not any(v.data_ptr() == g32.data_ptr() for v in results.values())
-        ref = results["f64"]
-        rec = {"stencil": stencil_name(r, box).replace("2d", "%dd" % ndim),
-               "interior": list(interior), "steps": T_STEPS}
-        for kind in ("f32", "f32c"):
-            nm = s5d.error_norms(results[kind], ref).cpu().numpy()
-            rec[kind] = {"max_abs_err": float(nm[0]), "max_rel_err": float(nm[2]),
-                         "rms_err": float(nm[3]), "normwise": float(nm[0] / nm[1])}
-        rec["f64_vs_oracle_sampled_rel"] = None
-        if ndim == 2:
-            g_host = g32.cpu().numpy().astype(np.float64)
-            prng = np.random.default_rng(7)
-            H = T_STEPS * r + r
-            worst = 0.0
-            for _ in range(3):
-                pt = tuple(int(v) for v in prng.integers(r, np.array(shape) - r))
-                lo = [max(0, pt[a] - H) for a in range(ndim)]
-                hi = [min(shape[a], pt[a] + H + 1) for a in range(ndim)]
-                win = g_host[tuple(slice(lo[a], hi[a]) for a in range(ndim))]
-                want = oracle.sweep(win, radius=r, box=box, coeffs=c, steps=T_STEPS)[
-                    tuple(pt[a] - lo[a] for a in range(ndim))]
-                worst = max(worst, abs(float(ref[pt].item()) - want) / abs(want))
-            rec["f64_vs_oracle_sampled_rel"] = worst
-        out.append(rec)
-        print("accuracy %s: f32 normwise %.3g, compensated %.3g" % (
-            rec["stencil"], rec["f32"]["normwise"], rec["f32c"]["normwise"]), file=sys.stderr,
-            flush=True)
-        del results, ref, g32
+    cases = []
+    if which in ("all", "2d"):
+        cases += [(2, r, box, (n2, n2)) for r, box in stencils2d]
+    if which in ("all", "3d"):
+        cases += [(3, 1, False, (n3,) * 3), (3, 1, True, (n3,) * 3)]
+    rows = []
+
+    def gpu_run(g, ndim, r, box, c, dtype, accum):
+        x = torch.from_numpy(g).to("cuda:0")
+        y = torch.empty_like(x)
+        p = s5d.Plan(ndim=ndim, radius=r, box=box, dtype=dtype, interior=tuple(s - 2 * r for s in g.shape),
+                     steps=T_STEPS, coeffs=c, accum=accum)
+        info = p.query()
+        idx = p.run(x, y)
+        torch.cuda.synchronize()
+        p.close()
+        out = (x if idx == 0 else y).cpu().numpy()
+        del x, y
         torch.cuda.empty_cache()
-    return out
+        return out, info
+
+    for ndim, r, box, interior in cases:
+        name = "%s%dd%dr %s" % ("box" if box else "star", ndim, r, "x".join(str(i) for i in interior))
+        rng = np.random.default_rng(si.workload_seed(1 if ndim == 2 else 2))
+        n = si.n_points(ndim, r, box)
+        c = si.random_coeffs(rng, n)
+        grid = si.random_grid(rng, si.padded_shape(interior, r))
+        t0 = time.perf_counter()
+        ref = oracle.sweep(grid, radius=r, box=box, coeffs=c, steps=T_STEPS)
+        t_or = time.perf_counter() - t0
+        print("accuracy-full %s: float64 oracle %.0f s" % (name, t_or), file=sys.stderr, flush=True)
+        got, info = gpu_run(grid, ndim, r, box, c, "f64", "plain")
+        row = _accuracy_row(name, "f64", got, ref, T_STEPS, n, float(grid.max()), "f64")
+        row.update(bt=info["bt"], kernel=("auto", "blocked", "direct")[info["kernel"]], oracle_s=t_or)
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+        del got, ref
+        g32, c32 = grid.astype(np.float32), c.astype(np.float32)
+        del grid
+        t0 = time.perf_counter()
+        ref = oracle.sweep(g32.astype(np.float64), radius=r, box=box, coeffs=c32.astype(np.float64),
+                           steps=T_STEPS)
+        t_or = time.perf_counter() - t0
+        print("accuracy-full %s: float64 oracle on float32 inputs %.0f s" % (name, t_or), file=sys.stderr,
+              flush=True)
+        for kind, accum in (("f32", "plain"), ("f32c", "compensated")):
+            got, info = gpu_run(g32, ndim, r, box, c32.astype(np.float64), "f32", accum)
+            row = _accuracy_row(name, kind, got, ref, T_STEPS, n, float(g32.max()),
+                                "plain" if accum == "plain" else "comp")
+            row.update(bt=info["bt"], kernel=("auto", "blocked", "direct")[info["kernel"]], oracle_s=t_or)
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+            del got
+        del ref, g32
+    if md:
+        cpu = _host_cpu()
+        with open(md, "w") as f:
+            f.write("# Whole-grid accuracy against the CPU oracle, T = 1000\n\n")
+            f.write("Command (from the repository root): `python bench.py --accuracy-full %s --md <this file>`\n\n"
+                    % which)
+            f.write("Oracle: the naive double-buffered loop in C (no FMA), OpenMP over axis 0, %d threads on "
+                    "%s.  Every cell of the GPU result is compared with the oracle's.  float64 rows: "
+                    "float64 inputs, bar 1e-12 on the normwise (max|g-o|/max|o|) and elementwise "
+                    "(max |g-o|/|o|) relative error.  float32 rows: float32-rounded grid and coefficients, "
+                    "compared with the float64 oracle run on those rounded inputs; bar on max|g-o|: "
+                    "T(gamma_n + u)max|A0| (plain), T(u + gamma_n^2)max|A0| (compensated), u = 2^-24.\n\n"
+                    % (cpu["cores"], cpu["cpu_model"] or "the host"))
+            f.write("| stencil | kind | b_T | kernel | max abs err | normwise rel | elementwise rel | "
+                    "bar | ok |\n|---|---|---|---|---|---|---|---|---|\n")
+            for row in rows:
+                f.write("| %s | %s | %d | %s | %.3e | %.3e | %.3e | %.3e | %s |\n" % (
+                    row["stencil"], row["kind"], row["bt"], row["kernel"], row["max_abs_err"],
+                    row["normwise"], row["elementwise"], row["bound"], "yes" if row["ok"] else "NO"))
+    return rows
 
 
 def summarize_pmc(d, kernel):
@@ -665,8 +907,12 @@ def main(argv=None):
     ap.add_argument("--serve", action="store_true", help="also measure the serving loop")
     ap.add_argument("--accuracy", action="store_true",
                     help="also report float32 and compensated errors against float64 after T steps")
+    ap.add_argument("--accuracy-full", nargs="?", const="all", choices=("all", "2d", "3d"),
+                    help="compare whole T = 1000 grids at the benchmark sizes with the CPU oracle")
+    ap.add_argument("--expr", action="store_true", help="time only the expression stencils")
+    ap.add_argument("--md", default=None, help="with --accuracy-full: write a markdown table here")
     ap.add_argument("--serve-requests", type=int, default=32)
-    ap.add_argument("--serve-loads", default="0.8")
+    ap.add_argument("--serve-loads", default="0.5,0.9")
     ap.add_argument("--serve-budgets-gib", default="64")
     ap.add_argument("--only-extras", action="store_true",
                     help="skip the headline sweep; print only the --batch/--serve records")
@@ -703,6 +949,12 @@ def main(argv=None):
     if args.full_sweep3d:
         full_sweep3d()
         return 0
+    if args.expr:
+        print(json.dumps(sweep_expr()))
+        return 0
+    if args.accuracy_full:
+        rows = accuracy_full(args.accuracy_full, args.md)
+        return 0 if all(r["ok"] for r in rows) else 1
 
     extras = {}
     if args.accuracy:
@@ -775,6 +1027,7 @@ def main(argv=None):
                       file=sys.stderr, flush=True)
         rec["bt_curve_star2d1r"] = curve
         rec["sweep3d_512"] = sweep3d_default()
+        rec["expression_stencils"] = sweep_expr()
     if not args.no_extras:
         # the metric's batched/served-vs-plain and p50/p99 parts, at their
         # default (short) sizes; --batch / --serve / --accuracy alone give
@@ -785,6 +1038,7 @@ def main(argv=None):
             extras["serving"] = bench_serve()
         if "accuracy" not in extras:
             extras["accuracy"] = bench_accuracy()
+        extras["plain_512_f64"] = bench_plain512()
     rec.update(extras)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(1, False, "f32")

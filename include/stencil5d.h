@@ -55,6 +55,7 @@ typedef int32_t s5d_status;
 #define S5D_ENOMEM 3       /* host allocation failed */
 #define S5D_EDEVICE 4      /* a HIP runtime call failed; see s5d_last_error() */
 #define S5D_EBUDGET 5      /* a memory budget would be exceeded */
+#define S5D_ECANCELED 6    /* a served request was cancelled (s5d_server_cancel) */
 
 /* Stencil shape (Background "Stencil Computation"). */
 #define S5D_STAR 0
@@ -69,6 +70,26 @@ typedef int32_t s5d_status;
 #define S5D_ACC_COMPENSATED 1 /* float32 only: error-free products and sums
                                  (compensated dot product), one final rounding */
 
+/* What a time step computes for an interior cell p (AN5D Table 3, the
+ * synthetic and the general benchmarks).  f is the previous time level. */
+#define S5D_EXPR_LINEAR 0   /* sum_k c_k f[p + o_k]: the star and box stencils.
+                               coeffs: the n points' weights in canonical order */
+#define S5D_EXPR_DIV 1      /* (sum_k c_k f[p + o_k]) / c0: j2d5pt (the program of
+                               Fig. 4), j2d9pt, j2d9pt-gol, j3d27pt.  coeffs: the n
+                               weights, then c0 (n_coeffs = n + 1).  Blocked kernels
+                               for the 2D star of radius 1 and 2, the 2D box and the
+                               3D box of radius 1, float32 and float64, plain
+                               accumulation */
+#define S5D_EXPR_GRADIENT 2 /* gradient2d, 2D star of radius 1 only:
+                               cc f[p] + 1 / sqrt(c0 + sum_n (f[p] - f[n])^2) over the
+                               four axis neighbours n in canonical order, each
+                               operation rounded on its own (no fused multiply-add).
+                               coeffs: cc, c0 (n_coeffs = 2) */
+#define S5D_EXPR_VARCOEF 3  /* sum_k C[k][q] f[p + o_k]: every interior cell has its
+                               own weights.  C is a device array passed to
+                               s5d_run_fields; coeffs is unused (n_coeffs = 0).  2D
+                               star of radius 1 and 2 and 2D box of radius 1 */
+
 /* Problem descriptor.  Set struct_size = sizeof(s5d_desc). */
 typedef struct s5d_desc {
     uint32_t struct_size;
@@ -76,12 +97,15 @@ typedef struct s5d_desc {
     int32_t radius;      /* stencil radius r >= 1 */
     int32_t shape;       /* S5D_STAR or S5D_BOX */
     int32_t dtype;       /* S5D_F32 or S5D_F64 */
-    int32_t accum;       /* S5D_ACC_PLAIN or S5D_ACC_COMPENSATED */
+    int32_t accum;       /* S5D_ACC_PLAIN or S5D_ACC_COMPENSATED (LINEAR only) */
     int64_t interior[3]; /* interior extents, axis 0 first; entries beyond ndim ignored */
     int64_t steps;       /* number of time steps T >= 0 */
-    const double *coeffs;/* host pointer, n_coeffs values in canonical offset order;
-                            copied by s5d_plan_create, not retained */
-    int64_t n_coeffs;    /* star: 2*radius*ndim + 1, box: (2*radius + 1)^ndim */
+    const double *coeffs;/* host pointer, n_coeffs values (see S5D_EXPR_*) in canonical
+                            offset order; copied by s5d_plan_create, not retained */
+    int64_t n_coeffs;    /* LINEAR: star 2*radius*ndim + 1, box (2*radius + 1)^ndim;
+                            DIV: that + 1; GRADIENT: 2; VARCOEF: 0 */
+    int32_t expr;        /* S5D_EXPR_* */
+    int32_t reserved;    /* 0 */
 } s5d_desc;
 
 /* Blocking parameters (AN5D "Execution Model", "Division of Streaming
@@ -98,7 +122,7 @@ typedef struct s5d_tuning {
                                h_SN >= 32) */
     int32_t cells_per_lane; /* consecutive cells of the last axis owned by one lane */
     int32_t rows_per_wave;  /* 3D: consecutive axis-1 rows held by one wave */
-    int32_t waves_per_eu;   /* reserved, 0 */
+    int32_t waves_per_eu;   /* reserved: must be 0 (S5D_EINVAL otherwise) */
     int32_t kernel;         /* S5D_KERNEL_*: which kernel family runs the sweep */
 } s5d_tuning;
 
@@ -149,6 +173,18 @@ s5d_status s5d_plan_query(const s5d_plan *plan, s5d_tuning *chosen, int64_t *byt
  * except launch failures (S5D_EDEVICE), which may leave a partial sweep. */
 s5d_status s5d_run(const s5d_plan *plan, void *buf0, void *buf1, void *stream,
                    int32_t *result_index);
+
+/* s5d_run for plans whose weights vary from cell to cell (S5D_EXPR_VARCOEF),
+ * which s5d_run rejects (S5D_EINVAL).
+ *   fields: device pointer, n_points arrays of the interior's extents
+ *           (I0 x I1, C order, the plan's dtype), weight k of every cell
+ *           first: fields[k * I0 * I1 + q] is the weight of offset k (canonical
+ *           order) for the interior cell with 0-based interior index q.  Read
+ *           by every round; the caller keeps it allocated and unchanged until
+ *           the stream has drained.
+ * Everything else is as for s5d_run.  fields must be NULL for other plans. */
+s5d_status s5d_run_fields(const s5d_plan *plan, void *buf0, void *buf1, const void *fields, void *stream,
+                          int32_t *result_index);
 
 /* ---- Performance model and autotuner ----
  *
@@ -220,7 +256,9 @@ typedef struct s5d_batch s5d_batch; /* opaque */
                              first run and replay it with one graph launch */
 
 /* Build a batch over n grids.  plans[i] (not retained: it may be destroyed
- * afterwards), buf0[i] and buf1[i] (device pointers, as for s5d_run) describe
+ * afterwards; the batch keeps a reference to whatever device state of the
+ * plan its launches read, such as the coefficient table of a direct kernel),
+ * buf0[i] and buf1[i] (device pointers, as for s5d_run) describe
  * grid i; the buffers are bound to the batch, must stay allocated while it
  * exists, and no two buffers of the batch may overlap.  The device tables are
  * allocated with hipMalloc on the current device and uploaded synchronously.
@@ -236,8 +274,8 @@ s5d_status s5d_batch_create(const s5d_plan *const *plans, void *const *buf0, voi
  * been reset.  Runs of one batch on different streams must not overlap. */
 s5d_status s5d_batch_run(s5d_batch *batch, void *stream, int32_t *result_index);
 
-/* Launches per run (boundary copies included) and the number of round
- * indices (may be NULL). */
+/* Launches per run (the one boundary-copy launch that covers every grid
+ * included) and the number of round indices (may be NULL). */
 s5d_status s5d_batch_query(const s5d_batch *batch, int32_t *n_launches, int32_t *n_round_steps);
 
 /* Wait for the device to drain, then release the batch (NULL accepted). */
@@ -250,17 +288,23 @@ s5d_status s5d_run_batch(const s5d_plan *const *plans, void *const *buf0, void *
 
 /* ---- Serving loop: continuous batching of sweep requests ----
  *
- * A server owns a HIP stream and the device memory of the grids it holds.
+ * A server owns HIP streams and the device memory of the grids it holds.
  * Requests (a plan and an initial grid) queue in arrival order.  Each call of
  * s5d_server_tick
- *   1. admits queued requests in FIFO order while the two buffers of the next
+ *   1. drops the running requests that were cancelled (FAILED, S5D_ECANCELED);
+ *   2. admits queued requests in FIFO order while the two buffers of the next
  *      one fit the HBM budget (and max_running allows it): stream-ordered
- *      allocation, copy of the initial grid, boundary copy;
- *   2. advances every running request by one round of its own schedule, all
- *      of them in one batched launch per kernel variant, so new arrivals join
- *      at round boundaries and every result is bit-identical to the request
- *      run alone with s5d_run;
- *   3. records when requests whose last round was just enqueued complete
+ *      allocation, copy of the initial grid, boundary copy.  A request whose
+ *      admission fails becomes FAILED and admission goes on with the next;
+ *   3. advances every running request by one round of its own schedule, all
+ *      of them in one batched launch per kernel variant (the variants of one
+ *      round spread over n_streams streams), so new arrivals join at round
+ *      boundaries and every result is bit-identical to the request run alone
+ *      with s5d_run.  A request's round counts as done only once its launch
+ *      has been enqueued: if a launch cannot be enqueued, requests with a
+ *      round in it become FAILED and the others are unaffected (if nothing of
+ *      the tick was enqueued, no request moves and the tick may be retried);
+ *   4. records when requests whose last round was just enqueued complete
  *      (GPU clock, on the server's time axis).
  * At most three ticks are in flight: a tick waits for the tick three before
  * it.  Times are seconds since s5d_server_create on the host's steady clock.
@@ -274,7 +318,13 @@ typedef struct s5d_server_config {
     int32_t rounds_per_tick;  /* rounds of each running request per tick; 0 = adaptive:
                                  ceil(8 / running), at most 16, so that a tick carries
                                  enough launches while few requests run */
-    int32_t reserved;
+    int32_t n_streams;        /* streams the launches of one round spread over, 1..4;
+                                 0 = 4 */
+    int32_t fail_admit_every; /* testing: k > 0 makes every k-th admission fail as if
+                                 its allocation had failed; 0 = off */
+    int32_t fail_tick_every;  /* testing: k > 0 makes the launch of the last round of
+                                 every k-th tick with work fail before it is enqueued;
+                                 0 = off */
 } s5d_server_config;
 
 /* Request states. */
@@ -282,21 +332,24 @@ typedef struct s5d_server_config {
 #define S5D_REQ_RUNNING 1
 #define S5D_REQ_DONE 2     /* finished; result held if it was kept */
 #define S5D_REQ_RELEASED 3 /* result fetched, memory returned */
+#define S5D_REQ_FAILED 4   /* will not finish (status says why); memory returned */
 
 typedef struct s5d_request_info {
     uint32_t struct_size; /* = sizeof(s5d_request_info) */
     int32_t state;        /* S5D_REQ_* */
     int32_t result_index; /* steps % 2 */
-    int32_t reserved;
+    int32_t status;       /* S5D_OK, or why a FAILED request failed */
     int64_t updates;      /* interior cells x steps */
     int64_t rounds_done;  /* rounds enqueued so far */
     double t_arrival, t_admit, t_done; /* seconds; -1 if not yet */
+    int32_t init_in_use;  /* 1 while the server may still read the request's init */
+    int32_t reserved;
 } s5d_request_info;
 
 typedef struct s5d_server_stats {
     uint32_t struct_size; /* = sizeof(s5d_server_stats) */
     int32_t reserved;
-    int64_t submitted, queued, running, done;
+    int64_t submitted, queued, running, done, failed;
     int64_t bytes_in_use, bytes_peak; /* grid memory held (both buffers per request) */
     int64_t ticks, launches;          /* ticks with work, batched launches they made */
     int64_t updates_done;             /* cell updates of the finished requests */
@@ -315,9 +368,11 @@ void s5d_server_destroy(s5d_server *server);
 s5d_status s5d_server_now(const s5d_server *server, double *seconds);
 
 /* Queue a request.  The plan is copied (the caller may destroy it).  `init`
- * (host or device memory, plan's padded grid, boundary included) is read when
- * the request is admitted, so it must stay valid until the request's state
- * leaves S5D_REQ_QUEUED.  `arrival` stamps the request on the server clock
+ * (host or device memory, plan's padded grid, boundary included) is read on
+ * the server's stream after the request is admitted, so it must stay valid
+ * and unchanged until s5d_server_request reports init_in_use = 0 (or the
+ * request is FAILED).  S5D_EUNSUPPORTED if a round of the plan has no batched
+ * kernel.  `arrival` stamps the request on the server clock
  * (negative: now).  With keep_result != 0 the result stays on the device until
  * s5d_server_fetch; otherwise it is dropped when the request completes.
  * S5D_EBUDGET if the request alone exceeds the budget. */
@@ -329,6 +384,12 @@ s5d_status s5d_server_submit(s5d_server *server, const s5d_plan *plan, const voi
  * request does not fit beside the kept results: it waits until they are
  * fetched. */
 s5d_status s5d_server_tick(s5d_server *server, int32_t *n_running, int32_t *n_queued);
+
+/* Cancel a request: a queued one becomes FAILED at once, a running one at the
+ * start of the next tick (its buffers are freed after the work already
+ * enqueued for it); finished requests are left as they are.  Status
+ * S5D_ECANCELED is recorded for it. */
+s5d_status s5d_server_cancel(s5d_server *server, int64_t id);
 
 /* Wait for all enqueued work and record the completions. */
 s5d_status s5d_server_sync(s5d_server *server);

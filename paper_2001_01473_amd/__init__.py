@@ -13,13 +13,14 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (ACC_COMPENSATED, ACC_PLAIN, BOX, F32, F64, STAR, Stencil5DError,
-                   last_error, status_string)
+from ._lib import (ACC_COMPENSATED, ACC_PLAIN, BOX, EXPR_DIV, EXPR_GRADIENT, EXPR_LINEAR,
+                   EXPR_VARCOEF, F32, F64, STAR, Stencil5DError, last_error, status_string)
 
 __all__ = ["Plan", "Batch", "Server", "solve", "error_norms", "autotune", "tune_cache_save",
            "tune_cache_load", "tune_cache_clear", "NORM_NAMES", "Stencil5DError", "status_string",
            "last_error",
-           "STAR", "BOX", "F32", "F64", "ACC_PLAIN", "ACC_COMPENSATED"]
+           "STAR", "BOX", "F32", "F64", "ACC_PLAIN", "ACC_COMPENSATED",
+           "EXPR_LINEAR", "EXPR_DIV", "EXPR_GRADIENT", "EXPR_VARCOEF"]
 
 _TUNING_KEYS = ("bt", "tile0", "tile1", "stream_chunk", "cells_per_lane", "rows_per_wave",
                 "waves_per_eu", "kernel")
@@ -40,6 +41,17 @@ def _dtype_code(dtype):
     raise ValueError("dtype must be float32 or float64, got %r" % (dtype,))
 
 
+_EXPRS = {"linear": EXPR_LINEAR, "div": EXPR_DIV, "gradient": EXPR_GRADIENT, "varcoef": EXPR_VARCOEF}
+
+
+def _expr_code(expr):
+    if isinstance(expr, int) and expr in _EXPRS.values():
+        return expr
+    if expr in _EXPRS:
+        return _EXPRS[expr]
+    raise ValueError("expr must be one of %s" % sorted(_EXPRS))
+
+
 def _accum_code(accum):
     if accum in (ACC_PLAIN, "plain"):
         return ACC_PLAIN
@@ -49,10 +61,15 @@ def _accum_code(accum):
 
 
 class Plan:
-    """An immutable sweep plan (``s5d_plan``): stencil, extents, steps, blocking."""
+    """An immutable sweep plan (``s5d_plan``): stencil, extents, steps, blocking.
 
-    def __init__(self, *, ndim, radius, box, dtype, interior, steps, coeffs,
-                 accum="plain", **tuning):
+    ``expr`` selects what a step computes (``S5D_EXPR_*`` of the C header):
+    "linear" (``coeffs``: the n weights), "div" (the n weights, then the
+    divisor c0), "gradient" (cc, c0) or "varcoef" (no ``coeffs``; the
+    per-cell weights are passed to ``run(..., fields=)``)."""
+
+    def __init__(self, *, ndim, radius, box, dtype, interior, steps, coeffs=None,
+                 accum="plain", expr="linear", **tuning):
         unknown = set(tuning) - set(_TUNING_KEYS)
         if unknown:
             raise TypeError("unknown tuning keys: %s" % sorted(unknown))
@@ -61,8 +78,9 @@ class Plan:
         self.dtype = _dtype_code(dtype)
         self.interior = tuple(int(i) for i in interior)
         self.steps = int(steps)
+        self.expr = _expr_code(expr)
         desc, keep = _lib.make_desc(ndim, radius, box, self.dtype, _accum_code(accum),
-                                    self.interior, steps, coeffs)
+                                    self.interior, steps, coeffs, self.expr)
         tun = _lib.make_tuning(**tuning) if tuning else None
         h = ctypes.c_void_p()
         st = lib.s5d_plan_create(ctypes.byref(desc), ctypes.byref(tun) if tun else None,
@@ -93,8 +111,10 @@ class Plan:
         out["bound"] = ("alu", "hbm", "lds")[m.bound]
         return out
 
-    def run(self, buf0, buf1, stream=None) -> int:
-        """Enqueue the sweep; returns the index (0/1) of the buffer holding the result."""
+    def run(self, buf0, buf1, stream=None, fields=None) -> int:
+        """Enqueue the sweep; returns the index (0/1) of the buffer holding the
+        result.  ``fields`` (variable-coefficient plans only): a contiguous
+        device tensor of the plan's dtype and shape (n_points,) + interior."""
         if self._h is None:
             raise RuntimeError("plan destroyed")
         import torch
@@ -110,9 +130,20 @@ class Plan:
             stream = torch.cuda.current_stream(buf0.device)
         handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
         idx = ctypes.c_int32(-1)
-        _lib.check(_lib.load().s5d_run(self._h, ctypes.c_void_p(buf0.data_ptr()),
-                                       ctypes.c_void_p(buf1.data_ptr()),
-                                       ctypes.c_void_p(handle), ctypes.byref(idx)), "s5d_run")
+        if fields is None:
+            _lib.check(_lib.load().s5d_run(self._h, ctypes.c_void_p(buf0.data_ptr()),
+                                           ctypes.c_void_p(buf1.data_ptr()),
+                                           ctypes.c_void_p(handle), ctypes.byref(idx)), "s5d_run")
+            return int(idx.value)
+        if not fields.is_cuda or not fields.is_contiguous() or _dtype_code(fields.dtype) != self.dtype:
+            raise ValueError("fields must be a contiguous device tensor of the plan's dtype")
+        if tuple(fields.shape[1:]) != self.interior:
+            raise ValueError("fields must have shape (n_points,) + interior")
+        _lib.check(_lib.load().s5d_run_fields(self._h, ctypes.c_void_p(buf0.data_ptr()),
+                                              ctypes.c_void_p(buf1.data_ptr()),
+                                              ctypes.c_void_p(fields.data_ptr()),
+                                              ctypes.c_void_p(handle), ctypes.byref(idx)),
+                   "s5d_run_fields")
         return int(idx.value)
 
     def close(self):
@@ -161,6 +192,7 @@ class Batch:
         self.n = n
         self._device = bufs0[0].device if n else None
         self._bufs = (list(bufs0), list(bufs1))  # keep the tensors alive
+        self._plans = list(plans)
         arr = vp * max(n, 1)
         hp = arr(*[p._h for p in plans])
         b0 = arr(*[vp(b.data_ptr()) for b in bufs0])
@@ -197,14 +229,14 @@ class Batch:
             pass
 
 
-def autotune(*, ndim, radius, box, dtype, interior, steps, coeffs, accum="plain", top_k=4,
-             stream=None):
+def autotune(*, ndim, radius, box, dtype, interior, steps, coeffs=None, accum="plain", top_k=4,
+             stream=None, expr="linear"):
     """Model-ranked, GPU-measured choice of the blocking for this problem
     (``s5d_autotune``); returns (tuning dict, report dict).  The choice is
     cached for later plans of the same stencil and extent bucket."""
     lib = _lib.load()
     desc, keep = _lib.make_desc(ndim, radius, box, _dtype_code(dtype), _accum_code(accum),
-                                interior, steps, coeffs)
+                                interior, steps, coeffs, _expr_code(expr))
     best = _lib.make_tuning()
     rep = _lib.S5DTuneReport()
     rep.struct_size = ctypes.sizeof(rep)
@@ -235,17 +267,21 @@ class Server:
     are admitted under an HBM budget and advance one round per ``tick()``,
     all running requests together.  Times are seconds on the server clock."""
 
-    def __init__(self, *, hbm_budget_bytes, max_running=0, rounds_per_tick=0):
+    def __init__(self, *, hbm_budget_bytes, max_running=0, rounds_per_tick=0, n_streams=0,
+                 fail_admit_every=0, fail_tick_every=0):
         lib = _lib.load()
         cfg = _lib.S5DServerConfig()
         cfg.struct_size = ctypes.sizeof(cfg)
         cfg.max_running = int(max_running)
         cfg.hbm_budget_bytes = int(hbm_budget_bytes)
         cfg.rounds_per_tick = int(rounds_per_tick)
+        cfg.n_streams = int(n_streams)
+        cfg.fail_admit_every = int(fail_admit_every)
+        cfg.fail_tick_every = int(fail_tick_every)
         h = ctypes.c_void_p()
         _lib.check(lib.s5d_server_create(ctypes.byref(cfg), ctypes.byref(h)), "s5d_server_create")
         self._h = h
-        self._inits = {}  # request id -> initial grid, kept alive until admitted
+        self._inits = {}  # request id -> initial grid, kept alive until the server has read it
 
     def now(self) -> float:
         t = ctypes.c_double()
@@ -283,8 +319,14 @@ class Server:
         self._drop_admitted()
         return int(nr.value), int(nq.value)
 
+    def cancel(self, rid):
+        """Cancel a queued or running request (it becomes FAILED with
+        S5D_ECANCELED; a running one leaves at the next tick)."""
+        _lib.check(_lib.load().s5d_server_cancel(self._h, int(rid)), "s5d_server_cancel")
+
     def sync(self):
         _lib.check(_lib.load().s5d_server_sync(self._h), "s5d_server_sync")
+        self._drop_admitted()
 
     def request(self, rid) -> dict:
         info = _lib.S5DRequestInfo()
@@ -308,11 +350,10 @@ class Server:
         return {k: getattr(st, k) for k, _ in st._fields_ if k not in ("struct_size", "reserved")}
 
     def _drop_admitted(self):
-        # admission is FIFO: stop at the first request still queued
+        # an initial grid may go once the server's copy of it has run
         for rid in sorted(self._inits):
-            if self.request(rid)["state"] == _lib.REQ_QUEUED:
-                break
-            del self._inits[rid]
+            if not self.request(rid)["init_in_use"]:
+                del self._inits[rid]
 
     def close(self):
         if getattr(self, "_h", None) is not None:
@@ -327,7 +368,8 @@ class Server:
             pass
 
 
-def solve(grid, *, radius, box, coeffs, steps, accum="plain", stream=None, **tuning):
+def solve(grid, *, radius, box, coeffs=None, steps, accum="plain", stream=None, expr="linear",
+          fields=None, **tuning):
     """Run ``steps`` time steps on a padded device grid; returns the result tensor.
 
     ``grid`` (float32/float64, contiguous, on the GPU, boundary included) is
@@ -337,9 +379,9 @@ def solve(grid, *, radius, box, coeffs, steps, accum="plain", stream=None, **tun
     import torch
     interior = tuple(s - 2 * radius for s in grid.shape)
     plan = Plan(ndim=grid.dim(), radius=radius, box=box, dtype=grid.dtype, interior=interior,
-                steps=steps, coeffs=coeffs, accum=accum, **tuning)
+                steps=steps, coeffs=coeffs, accum=accum, expr=expr, **tuning)
     other = torch.empty_like(grid)
-    idx = plan.run(grid, other, stream=stream)
+    idx = plan.run(grid, other, stream=stream, fields=fields)
     plan.close()
     return grid if idx == 0 else other
 

@@ -17,17 +17,18 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libstencil5d.so")
 
-S5D_OK, S5D_EINVAL, S5D_EUNSUPPORTED, S5D_ENOMEM, S5D_EDEVICE, S5D_EBUDGET = range(6)
+S5D_OK, S5D_EINVAL, S5D_EUNSUPPORTED, S5D_ENOMEM, S5D_EDEVICE, S5D_EBUDGET, S5D_ECANCELED = range(7)
 STAR, BOX = 0, 1
 F32, F64 = 0, 1
 ACC_PLAIN, ACC_COMPENSATED = 0, 1
+EXPR_LINEAR, EXPR_DIV, EXPR_GRADIENT, EXPR_VARCOEF = range(4)
 
 # Every symbol include/stencil5d.h declares.
-EXPORTS = ("s5d_plan_create", "s5d_plan_destroy", "s5d_plan_query", "s5d_run",
+EXPORTS = ("s5d_plan_create", "s5d_plan_destroy", "s5d_plan_query", "s5d_run", "s5d_run_fields",
            "s5d_batch_create", "s5d_batch_run", "s5d_batch_query", "s5d_batch_destroy",
            "s5d_run_batch",
            "s5d_server_create", "s5d_server_destroy", "s5d_server_now", "s5d_server_submit",
-           "s5d_server_tick", "s5d_server_sync", "s5d_server_request", "s5d_server_fetch",
+           "s5d_server_tick", "s5d_server_cancel", "s5d_server_sync", "s5d_server_request", "s5d_server_fetch",
            "s5d_server_get_stats",
            "s5d_plan_model", "s5d_autotune", "s5d_tune_cache_save", "s5d_tune_cache_load",
            "s5d_tune_cache_clear",
@@ -42,7 +43,8 @@ class S5DDesc(ctypes.Structure):
                 ("radius", ctypes.c_int32), ("shape", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("accum", ctypes.c_int32),
                 ("interior", ctypes.c_int64 * 3), ("steps", ctypes.c_int64),
-                ("coeffs", ctypes.POINTER(ctypes.c_double)), ("n_coeffs", ctypes.c_int64)]
+                ("coeffs", ctypes.POINTER(ctypes.c_double)), ("n_coeffs", ctypes.c_int64),
+                ("expr", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class S5DTuning(ctypes.Structure):
@@ -56,28 +58,30 @@ class S5DTuning(ctypes.Structure):
 class S5DServerConfig(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("max_running", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_int64), ("rounds_per_tick", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("n_streams", ctypes.c_int32), ("fail_admit_every", ctypes.c_int32),
+                ("fail_tick_every", ctypes.c_int32)]
 
 
 class S5DRequestInfo(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("state", ctypes.c_int32),
-                ("result_index", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("result_index", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("updates", ctypes.c_int64), ("rounds_done", ctypes.c_int64),
                 ("t_arrival", ctypes.c_double), ("t_admit", ctypes.c_double),
-                ("t_done", ctypes.c_double)]
+                ("t_done", ctypes.c_double), ("init_in_use", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class S5DServerStats(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("reserved", ctypes.c_int32),
                 ("submitted", ctypes.c_int64), ("queued", ctypes.c_int64),
                 ("running", ctypes.c_int64), ("done", ctypes.c_int64),
-                ("bytes_in_use", ctypes.c_int64), ("bytes_peak", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("bytes_in_use", ctypes.c_int64), ("bytes_peak", ctypes.c_int64),
                 ("ticks", ctypes.c_int64), ("launches", ctypes.c_int64),
                 ("updates_done", ctypes.c_int64), ("latency_p50", ctypes.c_double),
                 ("latency_p99", ctypes.c_double), ("makespan", ctypes.c_double)]
 
 
-REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_RELEASED = range(4)
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_RELEASED, REQ_FAILED = range(5)
 
 
 class S5DModel(ctypes.Structure):
@@ -134,6 +138,8 @@ def load():
                                        ctypes.POINTER(ctypes.c_int64)]
         lib.s5d_run.restype = ctypes.c_int32
         lib.s5d_run.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int32)]
+        lib.s5d_run_fields.restype = ctypes.c_int32
+        lib.s5d_run_fields.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int32)]
         vpp = ctypes.POINTER(vp)
         i32p = ctypes.POINTER(ctypes.c_int32)
         lib.s5d_batch_create.restype = ctypes.c_int32
@@ -158,6 +164,8 @@ def load():
         lib.s5d_server_submit.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int32, i64p]
         lib.s5d_server_tick.restype = ctypes.c_int32
         lib.s5d_server_tick.argtypes = [vp, i32p, i32p]
+        lib.s5d_server_cancel.restype = ctypes.c_int32
+        lib.s5d_server_cancel.argtypes = [vp, ctypes.c_int64]
         lib.s5d_server_sync.restype = ctypes.c_int32
         lib.s5d_server_sync.argtypes = [vp]
         lib.s5d_server_request.restype = ctypes.c_int32
@@ -203,8 +211,8 @@ def check(status: int, where: str):
         raise Stencil5DError(status, where, last_error())
 
 
-def make_desc(ndim, radius, box, dtype, accum, interior, steps, coeffs):
-    c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64))
+def make_desc(ndim, radius, box, dtype, accum, interior, steps, coeffs, expr=EXPR_LINEAR):
+    c = np.ascontiguousarray(np.asarray([] if coeffs is None else coeffs, dtype=np.float64).ravel())
     d = S5DDesc()
     d.struct_size = ctypes.sizeof(S5DDesc)
     d.ndim = int(ndim)
@@ -216,8 +224,10 @@ def make_desc(ndim, radius, box, dtype, accum, interior, steps, coeffs):
     for a in range(3):
         d.interior[a] = int(ext[a])
     d.steps = int(steps)
-    d.coeffs = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.coeffs = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if c.size else None
     d.n_coeffs = int(c.size)
+    d.expr = int(expr)
+    d.reserved = 0
     return d, c  # keep c alive while d is used
 
 

@@ -42,7 +42,7 @@ DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
                 "-I" + CSRC, "-I" + INCLUDE]
 
 HOST_SOURCES = ["abi.cpp", "batch.cpp", "server.cpp", "tune.cpp", "halo.hip", "norms.hip", "direct.hip"]
-HEADERS = ["s5d_internal.h", "kcommon.h", "sweep2d.h", "sweep3d.h"]
+HEADERS = ["s5d_internal.h", "kcommon.h", "sweep2d.h", "sweep3d.h", "sweepw2d.h"]
 HOST_HEADERS = ["host.h", "batch.h", "norms.h", "direct.h", "stream2d.h", "stream3d.h"]  # not included by the variant units
 
 # Kernel kinds: (name, C++ type, 32-bit words per element, accumulation
@@ -52,6 +52,18 @@ MAX_BT = 10
 # Compensated accumulation costs about nine VALU operations per term instead of
 # one FMA, so these kernels are bound by arithmetic already at small depth.
 MAX_BT_COMP = 4
+
+# Expressions (s5d_desc.expr): 0 the weighted sum, 1 the weighted sum divided
+# by c0, 2 gradient2d, 3 per-cell weights.  Expressions 2 and 3 run on the
+# window kernels (sweepw2d.h).
+EXPR_TAG = {0: "", 1: "div_", 2: "grad_", 3: "varc_"}
+# The expression stencils of the paper's general benchmarks (Table 3) that get
+# kernels: (expr, box, radius) -- j2d5pt, j2d9pt, j2d9pt-gol, gradient2d --
+# and the variable-coefficient stars and 3x3 box.
+EXPR_2D = [(1, 0, 1), (1, 0, 2), (1, 1, 1), (2, 0, 1), (3, 0, 1), (3, 0, 2), (3, 1, 1)]
+# Deepest fused depth compiled per expression (window kernels keep 2r+1 rows
+# per level; per-cell weights add n loads per cell and level).
+MAX_BT_EXPR = {1: 10, 2: 10, 3: 4}
 
 
 def est_vgprs_2d(words, box, r, cpl, bt, nr, accw=1):
@@ -73,11 +85,12 @@ def ring_depth(r, bt, words):
 
 
 def candidates_2d():
-    """(dtype, box, r, cpl, bt, nr) tuples worth compiling."""
+    """(dtype, expr, box, r, cpl, bt, nr) tuples worth compiling."""
     out = []
     for dtype, (_, _, words, acc) in DTYPES.items():
         cpls = (2, 4) if dtype == 1 else (4,)
-        for box, rmax in ((0, 4), (1, 2)):
+        # boxes of radius 3 and 4 (49 and 81 points) with plain accumulation
+        for box, rmax in ((0, 4), (1, 2 if acc else 4)):
             for r in range(1, rmax + 1):
                 for cpl in cpls:
                     if r > cpl:
@@ -88,8 +101,27 @@ def candidates_2d():
                         nr = ring_depth(r, bt, words)
                         if est_vgprs_2d(words, box, r, cpl, bt, nr, 1 + acc) > 224:
                             continue
-                        out.append((dtype, box, r, cpl, bt, nr))
+                        out.append((dtype, 0, box, r, cpl, bt, nr))
+    # expression stencils: plain float32 (4 cells per lane) and float64 (2)
+    for dtype in (0, 1):
+        words = DTYPES[dtype][2]
+        cpl = 4 if dtype == 0 else 2
+        for expr, box, r in EXPR_2D:
+            for bt in range(1, MAX_BT_EXPR[expr] + 1):
+                if 64 * cpl - 2 * bt * r < 16 * cpl:
+                    continue
+                nr = ring_depth(r, bt, words) if expr == 1 else window_ring(r)
+                rows = 2 * r + (1 if expr >= 2 else 0)
+                if words * (bt * rows * cpl + nr * cpl + cpl + 2 * r) + 16 > 224:
+                    continue
+                out.append((dtype, expr, box, r, cpl, bt, nr))
     return out
+
+
+def window_ring(r):
+    """Load ring of the window kernels: a divisor or multiple of the 2r+1-row
+    window, so the unrolled loop stays short (lcm(2r+1, NR) steps)."""
+    return 3 if r == 1 else 5
 
 
 def variants_2d():
@@ -117,7 +149,7 @@ def est_vgprs_3d(words, box, r, cpl, m, bt, nr, accw=1):
 
 
 def candidates_3d():
-    """(dtype, box, r, cpl, m, nw, bt, nr) tuples worth compiling."""
+    """(dtype, expr, box, r, cpl, m, nw, bt, nr) tuples worth compiling."""
     out = []
     for dtype, (_, _, words, acc) in DTYPES.items():
         for box in (0, 1):
@@ -136,7 +168,10 @@ def candidates_3d():
                             continue
                         if est_vgprs_3d(words, box, r, cpl, m, bt, 2, 1 + acc) > 0.85 * cap:
                             continue
-                        out.append((dtype, box, r, cpl, m, nw, bt, 2))
+                        out.append((dtype, 0, box, r, cpl, m, nw, bt, 2))
+                        # j3d27pt: the 27-point box divided by c0, plain float32 and float64
+                        if box and r == 1 and not acc and (cpl, m, nw) == TILES_3D[dtype][0 if dtype else 0]:
+                            out.append((dtype, 1, box, r, cpl, m, nw, bt, 2))
     return out
 
 
@@ -147,10 +182,20 @@ def variants_3d():
     return [v for v in candidates_3d() if _vname3(v) in rec and rec[_vname3(v)]["ok"]]
 
 
+def linear_variants_2d():
+    """Built variants of the weighted-sum stencils: (dtype, box, r, cpl, bt, nr)."""
+    return [(v[0],) + v[2:] for v in variants_2d() if v[1] == 0]
+
+
+def linear_variants_3d():
+    """Built 3D variants of the weighted-sum stencils: (dtype, box, r, cpl, m, nw, bt, nr)."""
+    return [(v[0],) + v[2:] for v in variants_3d() if v[1] == 0]
+
+
 def _vname3(v):
-    dtype, box, r, cpl, m, nw, bt, nr = v
-    return "k3d_%s_%s_r%d_c%d_m%d_w%d_b%d_n%d" % (DTYPES[dtype][0], "box" if box else "star",
-                                                  r, cpl, m, nw, bt, nr)
+    dtype, expr, box, r, cpl, m, nw, bt, nr = v
+    return "k3d_%s_%s%s_r%d_c%d_m%d_w%d_b%d_n%d" % (DTYPES[dtype][0], EXPR_TAG[expr], "box" if box else "star",
+                                                    r, cpl, m, nw, bt, nr)
 
 
 RESOURCES = os.path.join(HERE, "kernel_resources.json")
@@ -189,9 +234,9 @@ def _parse_resources(text):
 
 
 def _vname(v):
-    dtype, box, r, cpl, bt, nr = v
-    return "k2d_%s_%s_r%d_c%d_b%d_n%d" % (DTYPES[dtype][0], "box" if box else "star",
-                                          r, cpl, bt, nr)
+    dtype, expr, box, r, cpl, bt, nr = v
+    return "k2d_%s_%s%s_r%d_c%d_b%d_n%d" % (DTYPES[dtype][0], EXPR_TAG[expr], "box" if box else "star",
+                                            r, cpl, bt, nr)
 
 
 def _write_if_changed(path, text):
@@ -208,22 +253,28 @@ def _generate(variants, variants3=()):
     os.makedirs(inst, exist_ok=True)
     units = []
     for v in variants3:
-        dtype, box, r, cpl, m, nw, bt, nr = v
+        dtype, expr, box, r, cpl, m, nw, bt, nr = v
         name = _vname3(v)
         text = ('#include "sweep3d.h"\nnamespace s5d {\nKernel3D %s() {\n'
-                '  return make_kernel3d<%s, %d, %d, %s, %d, %d, %d, %d, %d>();\n}\n}  // namespace s5d\n'
-                % (name, DTYPES[dtype][1], DTYPES[dtype][3], r, "true" if box else "false", bt, cpl,
+                '  return make_kernel3d<%s, %d, %d, %d, %s, %d, %d, %d, %d, %d>();\n}\n}  // namespace s5d\n'
+                % (name, DTYPES[dtype][1], DTYPES[dtype][3], expr, r, "true" if box else "false", bt, cpl,
                    m, nw, nr))
         path = os.path.join(inst, name + ".hip")
         _write_if_changed(path, text)
         units.append(path)
     for v in variants:
-        dtype, box, r, cpl, bt, nr = v
+        dtype, expr, box, r, cpl, bt, nr = v
         name = _vname(v)
-        text = ('#include "sweep2d.h"\nnamespace s5d {\nKernel2D %s() {\n'
-                '  return make_kernel2d<%s, %d, %d, %s, %d, %d, %d>();\n}\n}  // namespace s5d\n'
-                % (name, DTYPES[dtype][1], DTYPES[dtype][3], r, "true" if box else "false", bt,
-                   cpl, nr))
+        if expr >= 2:
+            text = ('#include "sweepw2d.h"\nnamespace s5d {\nKernel2D %s() {\n'
+                    '  return make_kernelw2d<%s, %s, %d, %s, %d, %d, %d>();\n}\n}  // namespace s5d\n'
+                    % (name, DTYPES[dtype][1], "OP_GRADIENT" if expr == 2 else "OP_VARCOEF", r,
+                       "true" if box else "false", bt, cpl, nr))
+        else:
+            text = ('#include "sweep2d.h"\nnamespace s5d {\nKernel2D %s() {\n'
+                    '  return make_kernel2d<%s, %d, %d, %d, %s, %d, %d, %d>();\n}\n}  // namespace s5d\n'
+                    % (name, DTYPES[dtype][1], DTYPES[dtype][3], expr, r, "true" if box else "false", bt,
+                       cpl, nr))
         path = os.path.join(inst, name + ".hip")
         _write_if_changed(path, text)
         units.append(path)
@@ -231,17 +282,18 @@ def _generate(variants, variants3=()):
     lines += ["Kernel2D %s();" % _vname(v) for v in variants]
     lines.append("const Entry2D kRegistry2D[] = {")
     for v in variants:
-        dtype, box, r, cpl, bt, nr = v
-        lines.append("  {%d, %d, %d, %d, %d, &%s}," % (dtype, box, r, cpl, bt, _vname(v)))
+        dtype, expr, box, r, cpl, bt, nr = v
+        lines.append("  {%d, %d, %d, %d, %d, %d, &%s}," % (dtype, expr, box, r, cpl, bt, _vname(v)))
     lines.append("};")
     lines.append("const int kRegistry2DSize = %d;" % len(variants))
     lines += ["Kernel3D %s();" % _vname3(v) for v in variants3]
     lines.append("const Entry3D kRegistry3D[] = {")
     for v in variants3:
-        dtype, box, r, cpl, m, nw, bt, nr = v
-        lines.append("  {%d, %d, %d, %d, %d, %d, %d, &%s}," % (dtype, box, r, cpl, m, nw, bt, _vname3(v)))
+        dtype, expr, box, r, cpl, m, nw, bt, nr = v
+        lines.append("  {%d, %d, %d, %d, %d, %d, %d, %d, &%s}," % (dtype, expr, box, r, cpl, m, nw, bt,
+                                                                 _vname3(v)))
     if not variants3:
-        lines.append("  {0, 0, 0, 0, 0, 0, 0, nullptr},")
+        lines.append("  {0, 0, 0, 0, 0, 0, 0, 0, nullptr},")
     lines.append("};")
     lines.append("const int kRegistry3DSize = %d;" % len(variants3))
     lines.append("}  // namespace s5d")
@@ -299,9 +351,24 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
     cands = [v for v in candidates_2d() if only is None or re.search(only, _vname(v))]
     cands3 = [v for v in candidates_3d() if only is None or re.search(only, _vname3(v))]
     units, _ = _generate(cands, cands3)
-    # kernel units include only the device headers; host sources also the
-    # public header and the host-side internal headers
+    # kernel units include only the device headers they use (a 3D unit does
+    # not see the 2D sweep, and so on); host sources also the public header and
+    # the host-side internal headers
     hdr = _digest([os.path.join(CSRC, h) for h in HEADERS], [])
+    base_hdr = ["s5d_internal.h", "kcommon.h"]
+    unit_hdr = {
+        "2d": _digest([os.path.join(CSRC, h) for h in base_hdr + ["sweep2d.h"]], []),
+        "w2d": _digest([os.path.join(CSRC, h) for h in base_hdr + ["sweep2d.h", "sweepw2d.h"]], []),
+        "3d": _digest([os.path.join(CSRC, h) for h in base_hdr + ["sweep3d.h"]], []),
+    }
+
+    def key_of_unit(path):
+        name = os.path.basename(path)
+        if name.startswith("k3d_"):
+            return unit_hdr["3d"]
+        if "_grad_" in name or "_varc_" in name:
+            return unit_hdr["w2d"]
+        return unit_hdr["2d"]
     jobs = jobs or max(1, min(32, os.cpu_count() or 1))
     t0 = time.time()
     objs, res_by_unit = {}, {}
@@ -311,7 +378,7 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
     # longest first: the box and deep variants dominate the build time
     order = sorted(units, key=lambda p: (("box" not in p), -len(p))) + host
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        futs = {ex.submit(_compile, s, host_hdr if s in host else hdr, incremental): s
+        futs = {ex.submit(_compile, s, host_hdr if s in host else key_of_unit(s), incremental): s
                 for s in order}
         for fut in cf.as_completed(futs):
             obj, dt, resources = fut.result()

@@ -58,10 +58,11 @@ int max_radius(int ndim, int shape) {
   return 4;
 }
 
-const Entry3D* find3d(int kind, int box, int r, int cpl, int m, int nw, int bt) {
+const Entry3D* find3d(int kind, int expr, int box, int r, int cpl, int m, int nw, int bt) {
   for (int i = 0; i < s5d::kRegistry3DSize; ++i) {
     const Entry3D& e = s5d::kRegistry3D[i];
-    if (e.dtype == kind && e.box == box && e.r == r && e.cpl == cpl && e.m == m && e.nw == nw && e.bt == bt)
+    if (e.dtype == kind && e.expr == expr && e.box == box && e.r == r && e.cpl == cpl && e.m == m && e.nw == nw &&
+        e.bt == bt)
       return &e;
   }
   return nullptr;
@@ -76,7 +77,8 @@ struct Default3D {
   int bt, m;
   int hmin = 0;  // stream-block floor (planes), for extents of at least 4 * hmin
 };
-Default3D default_tuning3(int kind, int box, int r) {
+Default3D default_tuning3(int kind, int box, int r, int expr = 0) {
+  if (expr == s5d::EXPR_DIV) return kind == KIND_F64 ? Default3D{2, 2} : Default3D{2, 4};
   if (kind == KIND_F32_COMP) return {1, 2};
   if (kind == KIND_F64) {
     if (r == 1) return box ? Default3D{2, 4} : Default3D{3, 2};
@@ -85,7 +87,7 @@ Default3D default_tuning3(int kind, int box, int r) {
   if (r == 1) return box ? Default3D{2, 4, 64} : Default3D{3, 4};
   return box ? Default3D{1, 4} : Default3D{2, 4};
 }
-int default_bt3(int kind, int box, int r) { return default_tuning3(kind, box, r).bt; }
+int default_bt3(int kind, int box, int r, int expr) { return default_tuning3(kind, box, r, expr).bt; }
 
 // Stencils whose direct kernel measured faster than every blocked variant
 // on MI355X at 512^3: the 125-point float32 box, the compensated 27-point
@@ -98,34 +100,34 @@ bool prefer_direct(int kind, int ndim, int box, int r) {
 }
 
 // Is any blocked variant compiled for this stencil?
-bool has_blocked(int kind, int ndim, int box, int r) {
+bool has_blocked(int kind, int expr, int ndim, int box, int r) {
   if (ndim == 2) {
     for (int i = 0; i < s5d::kRegistry2DSize; ++i) {
       const Entry2D& e = s5d::kRegistry2D[i];
-      if (e.dtype == kind && e.box == box && e.r == r) return true;
+      if (e.dtype == kind && e.expr == expr && e.box == box && e.r == r) return true;
     }
     return false;
   }
   for (int i = 0; i < s5d::kRegistry3DSize; ++i) {
     const Entry3D& e = s5d::kRegistry3D[i];
-    if (e.dtype == kind && e.box == box && e.r == r) return true;
+    if (e.dtype == kind && e.expr == expr && e.box == box && e.r == r) return true;
   }
   return false;
 }
 
-const Entry2D* find2d(int kind, int box, int r, int cpl, int bt) {
+const Entry2D* find2d(int kind, int expr, int box, int r, int cpl, int bt) {
   for (int i = 0; i < s5d::kRegistry2DSize; ++i) {
     const Entry2D& e = s5d::kRegistry2D[i];
-    if (e.dtype == kind && e.box == box && e.r == r && e.cpl == cpl && e.bt == bt) return &e;
+    if (e.dtype == kind && e.expr == expr && e.box == box && e.r == r && e.cpl == cpl && e.bt == bt) return &e;
   }
   return nullptr;
 }
 
-int max_bt2d(int kind, int box, int r, int cpl) {
+int max_bt2d(int kind, int expr, int box, int r, int cpl) {
   int best = 0;
   for (int i = 0; i < s5d::kRegistry2DSize; ++i) {
     const Entry2D& e = s5d::kRegistry2D[i];
-    if (e.dtype == kind && e.box == box && e.r == r && e.cpl == cpl) best = std::max(best, e.bt);
+    if (e.dtype == kind && e.expr == expr && e.box == box && e.r == r && e.cpl == cpl) best = std::max(best, e.bt);
   }
   return best;
 }
@@ -138,18 +140,29 @@ int max_bt2d(int kind, int box, int r, int cpl) {
 struct Default2D {
   int bt, cpl;
 };
-Default2D default_tuning(int kind, int box, int r) {
+Default2D default_tuning(int kind, int box, int r, int expr = 0) {
+  // expression stencils: the division costs an IEEE quotient per cell and
+  // level, gradient2d a square root and a quotient (bound by arithmetic from
+  // b_T = 2 on), per-cell weights n extra loads per cell and level; one tile
+  // width each (4 float32 / 2 float64 cells per lane)
+  if (expr == s5d::EXPR_GRADIENT || expr == s5d::EXPR_VARCOEF) return {2, kind == KIND_F64 ? 2 : 4};
+  if (expr == s5d::EXPR_DIV) {
+    const int c = kind == KIND_F64 ? 2 : 4;
+    if (box) return {kind == KIND_F64 ? 6 : 5, c};
+    return {r == 1 ? 8 : 5, c};
+  }
   static const Default2D f32_star[4] = {{10, 4}, {7, 4}, {5, 4}, {3, 4}};
-  static const Default2D f32_box[2] = {{7, 4}, {3, 4}};
+  static const Default2D f32_box[4] = {{7, 4}, {3, 4}, {2, 4}, {2, 4}};
   static const Default2D f64_star[4] = {{10, 2}, {6, 2}, {3, 4}, {2, 4}};
-  static const Default2D f64_box[2] = {{9, 2}, {4, 2}};
+  static const Default2D f64_box[4] = {{9, 2}, {4, 2}, {2, 4}, {2, 4}};
   static const Default2D comp_star[4] = {{3, 4}, {3, 4}, {1, 4}, {1, 4}};
-  static const Default2D comp_box[2] = {{3, 4}, {1, 4}};
-  if (kind == KIND_F32) return box ? f32_box[r - 1] : f32_star[r - 1];
-  if (kind == KIND_F32_COMP) return box ? comp_box[r - 1] : comp_star[r - 1];
-  return box ? f64_box[r - 1] : f64_star[r - 1];
+  static const Default2D comp_box[4] = {{3, 4}, {1, 4}, {1, 4}, {1, 4}};
+  const int i = std::min(std::max(r, 1), 4) - 1;  // radius 1..4 (larger radii have no kernels)
+  if (kind == KIND_F32) return box ? f32_box[i] : f32_star[i];
+  if (kind == KIND_F32_COMP) return box ? comp_box[i] : comp_star[i];
+  return box ? f64_box[i] : f64_star[i];
 }
-int default_bt(int kind, int box, int r) { return default_tuning(kind, box, r).bt; }
+int default_bt(int kind, int box, int r, int expr) { return default_tuning(kind, box, r, expr).bt; }
 
 struct DeviceInfo {
   int cus = 256;
@@ -293,17 +306,18 @@ s5d_status plan_2d(s5d_plan* p, const s5d_tuning& req, int box, int r) {
   }
   if (req.tile1 > 0 || req.rows_per_wave > 0) return fail(S5D_EINVAL, "tile1 and rows_per_wave are 3D fields");
   int bt = req.bt;
+  const int ex = p->expr;
   if (cpl == 0) {
     // the default tile width, if it is built to the requested (or default) depth
-    const int c = default_tuning(p->kind, box, r).cpl;
-    if (max_bt2d(p->kind, box, r, c) >= (bt > 0 ? bt : default_bt(p->kind, box, r))) cpl = c;
+    const int c = default_tuning(p->kind, box, r, ex).cpl;
+    if (max_bt2d(p->kind, ex, box, r, c) >= (bt > 0 ? bt : default_bt(p->kind, box, r, ex))) cpl = c;
   }
   if (cpl == 0) {
     // widest tile that still reaches the requested (or default) depth
-    const int want = bt > 0 ? bt : default_bt(p->kind, box, r);
+    const int want = bt > 0 ? bt : default_bt(p->kind, box, r, ex);
     int best_cpl = 0, best_bt = 0;
     for (int c : {4, 2, 8}) {
-      const int mb = std::min(want, max_bt2d(p->kind, box, r, c));
+      const int mb = std::min(want, max_bt2d(p->kind, ex, box, r, c));
       if (mb > best_bt) {
         best_bt = mb;
         best_cpl = c;
@@ -312,15 +326,15 @@ s5d_status plan_2d(s5d_plan* p, const s5d_tuning& req, int box, int r) {
     if (best_cpl == 0) return fail(S5D_EUNSUPPORTED, "no kernel variant for this stencil");
     cpl = best_cpl;
   }
-  const int bt_cap = max_bt2d(p->kind, box, r, cpl);
+  const int bt_cap = max_bt2d(p->kind, ex, box, r, cpl);
   if (bt_cap == 0) return fail(S5D_EUNSUPPORTED, "no kernel with cells_per_lane=" + std::to_string(cpl));
-  if (bt == 0) bt = std::min(default_bt(p->kind, box, r), bt_cap);
+  if (bt == 0) bt = std::min(default_bt(p->kind, box, r, ex), bt_cap);
   if (bt > bt_cap)
     return fail(S5D_EUNSUPPORTED, "bt=" + std::to_string(bt) + " exceeds the deepest kernel built for this stencil (" +
                                       std::to_string(bt_cap) + ")");
   if (d.steps > 0 && bt > d.steps) bt = static_cast<int>(d.steps);
   for (int b = 1; b <= bt; ++b) {
-    const Entry2D* e = find2d(p->kind, box, r, cpl, b);
+    const Entry2D* e = find2d(p->kind, ex, box, r, cpl, b);
     if (!e) return fail(S5D_EUNSUPPORTED, "kernel variant missing for bt=" + std::to_string(b));
     p->by_bt[b] = e->make();
   }
@@ -353,16 +367,17 @@ s5d_status plan_3d(s5d_plan* p, const s5d_tuning& req, int box, int r) {
   int bt_cap = 0;
   // without an explicit shape, the default family if it is built
   int want_m = req.rows_per_wave;
+  const int ex = p->expr;
   if (want_m == 0 && req.cells_per_lane == 0 && req.tile0 == 0 && req.tile1 == 0) {
-    const int m = default_tuning3(p->kind, box, r).m;
+    const int m = default_tuning3(p->kind, box, r, ex).m;
     for (int i = 0; i < s5d::kRegistry3DSize && want_m == 0; ++i) {
       const Entry3D& e = s5d::kRegistry3D[i];
-      if (e.dtype == p->kind && e.box == box && e.r == r && e.m == m) want_m = m;
+      if (e.dtype == p->kind && e.expr == ex && e.box == box && e.r == r && e.m == m) want_m = m;
     }
   }
   for (int i = 0; i < s5d::kRegistry3DSize; ++i) {
     const Entry3D& e = s5d::kRegistry3D[i];
-    if (e.dtype != p->kind || e.box != box || e.r != r) continue;
+    if (e.dtype != p->kind || e.expr != ex || e.box != box || e.r != r) continue;
     if (req.cells_per_lane > 0 && e.cpl != req.cells_per_lane) continue;
     if (want_m > 0 && e.m != want_m) continue;
     if (req.tile0 > 0 && e.m * e.nw != req.tile0) continue;
@@ -373,13 +388,13 @@ s5d_status plan_3d(s5d_plan* p, const s5d_tuning& req, int box, int r) {
     }
   }
   if (!fam) return fail(S5D_EUNSUPPORTED, "no 3D kernel for this stencil and tile shape");
-  int bt = req.bt > 0 ? req.bt : std::min(default_bt3(p->kind, box, r), bt_cap);
+  int bt = req.bt > 0 ? req.bt : std::min(default_bt3(p->kind, box, r, ex), bt_cap);
   if (bt > bt_cap)
     return fail(S5D_EUNSUPPORTED, "bt=" + std::to_string(bt) + " exceeds the deepest 3D kernel built (" +
                                       std::to_string(bt_cap) + ")");
   if (d.steps > 0 && bt > d.steps) bt = static_cast<int>(d.steps);
   for (int b = 1; b <= bt; ++b) {
-    const Entry3D* e = find3d(p->kind, box, r, fam->cpl, fam->m, fam->nw, b);
+    const Entry3D* e = find3d(p->kind, ex, box, r, fam->cpl, fam->m, fam->nw, b);
     if (!e) return fail(S5D_EUNSUPPORTED, "3D kernel variant missing for bt=" + std::to_string(b));
     p->by_bt3[b] = e->make();
   }
@@ -393,7 +408,7 @@ s5d_status plan_3d(s5d_plan* p, const s5d_tuning& req, int box, int r) {
     const int64_t ntiles = ((d.interior[1] + C1 - 1) / C1) * ((d.interior[2] + C2 - 1) / C2);
     const int64_t slots = static_cast<int64_t>(dev.cus) * occ;  // resident workgroups
     chunk = choose_chunk(d.interior[0], ntiles, slots, bt, r);
-    const Default3D def = default_tuning3(p->kind, box, r);
+    const Default3D def = default_tuning3(p->kind, box, r, ex);
     if (def.hmin > 0 && bt == def.bt && fam->m == def.m && d.interior[0] >= 4LL * def.hmin)
       chunk = std::max(chunk, def.hmin);
   }
@@ -421,8 +436,9 @@ std::vector<int> plan_rounds(const s5d_plan* p) {
 }
 
 namespace {
-Round2D round2d(const s5d_plan* p, const void* src, void* dst, hipStream_t stream) {
+Round2D round2d(const s5d_plan* p, const void* src, void* dst, hipStream_t stream, const void* fields = nullptr) {
   Round2D rd;
+  rd.fields = fields;
   rd.dcoef = p->dcoef.get();
   rd.src = src;
   rd.dst = dst;
@@ -448,9 +464,10 @@ Round3D round3d(const s5d_plan* p, const void* src, void* dst, hipStream_t strea
 }
 }  // namespace
 
-hipError_t launch_round(const s5d_plan* p, int bt, const void* src, void* dst, hipStream_t stream) {
+hipError_t launch_round(const s5d_plan* p, int bt, const void* src, void* dst, hipStream_t stream,
+                        const void* fields) {
   if (p->d.ndim == 3) return p->by_bt3[bt].launch(round3d(p, src, dst, stream));
-  return p->by_bt[bt].launch(round2d(p, src, dst, stream));
+  return p->by_bt[bt].launch(round2d(p, src, dst, stream, fields));
 }
 
 BatchHooks batch_hooks(const s5d_plan* p, int bt) {
@@ -504,6 +521,7 @@ const char* s5d_status_string(s5d_status status) {
     case S5D_ENOMEM: return "S5D_ENOMEM";
     case S5D_EDEVICE: return "S5D_EDEVICE";
     case S5D_EBUDGET: return "S5D_EBUDGET";
+    case S5D_ECANCELED: return "S5D_ECANCELED";
     default: return "S5D_UNKNOWN";
   }
 }
@@ -527,13 +545,25 @@ s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_p
     return fail(S5D_EINVAL, "compensated accumulation is defined for float32 grids only");
   if (d.steps < 0) return fail(S5D_EINVAL, "steps must be >= 0");
   if (d.radius > 64) return fail(S5D_EINVAL, "radius out of range");
-  int64_t n_expected = d.shape == S5D_BOX ? 1 : 2LL * d.radius * d.ndim + 1;
+  if (d.expr < S5D_EXPR_LINEAR || d.expr > S5D_EXPR_VARCOEF)
+    return fail(S5D_EINVAL, "expr must be one of S5D_EXPR_LINEAR, _DIV, _GRADIENT, _VARCOEF");
+  if (d.reserved != 0) return fail(S5D_EINVAL, "desc->reserved must be 0");
+  if (d.expr != S5D_EXPR_LINEAR && d.accum != S5D_ACC_PLAIN)
+    return fail(S5D_EUNSUPPORTED, "compensated accumulation is built for the linear stencils only");
+  if (d.expr == S5D_EXPR_GRADIENT && (d.ndim != 2 || d.radius != 1 || d.shape != S5D_STAR))
+    return fail(S5D_EINVAL, "gradient2d is the 2D star of radius 1");
+  int64_t n_points = d.shape == S5D_BOX ? 1 : 2LL * d.radius * d.ndim + 1;
   if (d.shape == S5D_BOX)
-    for (int a = 0; a < d.ndim; ++a) n_expected *= 2LL * d.radius + 1;
+    for (int a = 0; a < d.ndim; ++a) n_points *= 2LL * d.radius + 1;
+  const int64_t n_expected = d.expr == S5D_EXPR_LINEAR ? n_points
+                             : d.expr == S5D_EXPR_DIV  ? n_points + 1
+                             : d.expr == S5D_EXPR_GRADIENT ? 2
+                                                           : 0;
   if (d.n_coeffs != n_expected)
-    return fail(S5D_EINVAL, "n_coeffs is " + std::to_string(d.n_coeffs) + ", the stencil has " +
-                                std::to_string(n_expected) + " points");
-  if (!d.coeffs) return fail(S5D_EINVAL, "coeffs is NULL");
+    return fail(S5D_EINVAL, "n_coeffs is " + std::to_string(d.n_coeffs) + ", the stencil and expression take " +
+                                std::to_string(n_expected));
+  if (n_expected > 0 && !d.coeffs) return fail(S5D_EINVAL, "coeffs is NULL");
+  if (d.expr == S5D_EXPR_DIV && d.coeffs[n_expected - 1] == 0.0) return fail(S5D_EINVAL, "the divisor c0 is 0");
   for (int64_t k = 0; k < d.n_coeffs; ++k)
     if (!std::isfinite(d.coeffs[k])) return fail(S5D_EINVAL, "coefficient " + std::to_string(k) + " is not finite");
   int64_t total = 1;
@@ -562,6 +592,7 @@ s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_p
     if (req.kernel != S5D_KERNEL_AUTO && req.kernel != S5D_KERNEL_BLOCKED && req.kernel != S5D_KERNEL_DIRECT)
       return fail(S5D_EINVAL, "kernel must be S5D_KERNEL_AUTO, _BLOCKED or _DIRECT");
     if (req.bt > 15) return fail(S5D_EINVAL, "bt must be <= 15");
+    if (req.waves_per_eu != 0) return fail(S5D_EINVAL, "waves_per_eu is reserved and must be 0");
   }
 
   if (d.radius > max_radius(d.ndim, d.shape))
@@ -572,8 +603,9 @@ s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_p
   s5d_plan* p = new (std::nothrow) s5d_plan;
   if (!p) return fail(S5D_ENOMEM, "plan allocation failed");
   p->d = d;
+  p->expr = d.expr;
   try {
-    p->coeffs.assign(d.coeffs, d.coeffs + d.n_coeffs);
+    if (d.n_coeffs > 0) p->coeffs.assign(d.coeffs, d.coeffs + d.n_coeffs);
   } catch (...) {
     delete p;
     return fail(S5D_ENOMEM, "coefficient copy failed");
@@ -605,6 +637,10 @@ s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_p
     if (st != S5D_OK) {
       g_last_error.clear();
       reset();
+    } else {
+      // the library chose it (through the tuner), not the caller: batches and
+      // servers may still size the stream blocks for a grid's share
+      p->chunk_auto = true;
     }
   }
   const bool no_blocking = req.bt <= 1 && req.cells_per_lane == 0 && req.rows_per_wave == 0 && req.tile0 == 0 &&
@@ -612,19 +648,23 @@ s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_p
   // b_T = 1 asked for: the row-streaming direct kernel (plain accumulation;
   // 2D stars and boxes of radius <= 2, the 3D 7-point star) is faster than
   // the blocked kernel at depth 1
-  const bool stream_bt1 = req.kernel == S5D_KERNEL_AUTO && no_blocking && req.bt == 1 &&
+  const bool linear = d.expr == S5D_EXPR_LINEAR;
+  if (!linear && req.kernel == S5D_KERNEL_DIRECT)
+    return fail(S5D_EUNSUPPORTED, "expression stencils run on the blocked kernels only");
+  const bool stream_bt1 = linear && req.kernel == S5D_KERNEL_AUTO && no_blocking && req.bt == 1 &&
                           p->kind != KIND_F32_COMP &&
                           ((d.ndim == 2 && (!box || r <= 2)) || (d.ndim == 3 && !box && r == 1));
   if (st != S5D_OK) {
     if (req.kernel == S5D_KERNEL_DIRECT || stream_bt1 ||
-        (req.kernel == S5D_KERNEL_AUTO && no_blocking && req.bt == 0 && prefer_direct(p->kind, d.ndim, box, r))) {
+        (linear && req.kernel == S5D_KERNEL_AUTO && no_blocking && req.bt == 0 &&
+         prefer_direct(p->kind, d.ndim, box, r))) {
       st = plan_direct(p, req, box, r);
     } else {
       st = d.ndim == 2 ? plan_2d(p, req, box, r) : plan_3d(p, req, box, r);
       // no blocked variant for this stencil: the direct kernels, unless the
       // caller asked for blocking or gave blocking parameters
-      if (st == S5D_EUNSUPPORTED && req.kernel == S5D_KERNEL_AUTO && no_blocking &&
-          !has_blocked(p->kind, d.ndim, box, r)) {
+      if (st == S5D_EUNSUPPORTED && linear && req.kernel == S5D_KERNEL_AUTO && no_blocking &&
+          !has_blocked(p->kind, 0, d.ndim, box, r)) {
         g_last_error.clear();
         reset();
         st = plan_direct(p, req, box, r);
@@ -655,7 +695,19 @@ s5d_status s5d_plan_query(const s5d_plan* plan, s5d_tuning* chosen, int64_t* byt
 
 s5d_status s5d_run(const s5d_plan* plan, void* buf0, void* buf1, void* stream, int32_t* result_index) {
   g_last_error.clear();
+  if (plan && plan->expr == S5D_EXPR_VARCOEF)
+    return fail(S5D_EINVAL, "a plan with per-cell weights runs through s5d_run_fields");
+  return s5d_run_fields(plan, buf0, buf1, nullptr, stream, result_index);
+}
+
+s5d_status s5d_run_fields(const s5d_plan* plan, void* buf0, void* buf1, const void* fields, void* stream,
+                          int32_t* result_index) {
+  g_last_error.clear();
   if (!plan) return fail(S5D_EINVAL, "plan is NULL");
+  if ((plan->expr == S5D_EXPR_VARCOEF) != (fields != nullptr))
+    return fail(S5D_EINVAL, plan->expr == S5D_EXPR_VARCOEF ? "fields is NULL" : "fields given for a plan without per-cell weights");
+  if (fields && (reinterpret_cast<uintptr_t>(fields) % plan->elem) != 0)
+    return fail(S5D_EINVAL, "fields not aligned to the element size");
   const s5d_status bst = s5d::check_buffers(plan, buf0, buf1);
   if (bst != S5D_OK) return bst;
   const int64_t T = plan->d.steps;
@@ -668,7 +720,7 @@ s5d_status s5d_run(const s5d_plan* plan, void* buf0, void* buf1, void* stream, i
   void* bufs[2] = {buf0, buf1};
   const std::vector<int> rounds = s5d::plan_rounds(plan);
   for (size_t k = 0; k < rounds.size(); ++k) {
-    e = s5d::launch_round(plan, rounds[k], bufs[k % 2], bufs[(k + 1) % 2], st);
+    e = s5d::launch_round(plan, rounds[k], bufs[k % 2], bufs[(k + 1) % 2], st, fields);
     if (e != hipSuccess) return device_fail(e, "sweep launch");
   }
   return S5D_OK;

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <new>
 #include <vector>
 
@@ -82,23 +83,63 @@ s5d_status build_step(const std::vector<RoundItem>& items, std::vector<unsigned 
   return S5D_OK;
 }
 
+hipError_t StepStreams::create(int n) {
+  n_side = 0;
+  hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    fork = nullptr;
+    return e;
+  }
+  for (int i = 0; i < n && i < kMaxSideStreams; ++i) {
+    e = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      side[i] = nullptr;
+      return e;
+    }
+    e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      join[i] = nullptr;
+      return e;
+    }
+    n_side = i + 1;
+  }
+  return hipSuccess;
+}
+
+void StepStreams::destroy() {
+  for (int i = 0; i < kMaxSideStreams; ++i) {
+    if (side[i]) (void)hipStreamSynchronize(side[i]);
+    if (side[i]) (void)hipStreamDestroy(side[i]);
+    if (join[i]) (void)hipEventDestroy(join[i]);
+    side[i] = nullptr;
+    join[i] = nullptr;
+  }
+  if (fork) (void)hipEventDestroy(fork);
+  fork = nullptr;
+  n_side = 0;
+}
+
 hipError_t enqueue_step(const std::vector<GroupLaunch>& launches, const unsigned char* dev, hipStream_t stream,
-                        hipStream_t side, hipEvent_t fork, hipEvent_t join) {
-  const bool split = side && fork && join && launches.size() >= 2;
+                        const StepStreams* ss) {
+  const int nside = (ss && ss->fork && launches.size() >= 2)
+                        ? std::min<int>(ss->n_side, static_cast<int>(launches.size()) - 1)
+                        : 0;
   hipError_t e = hipSuccess;
-  if (split) {
-    if ((e = hipEventRecord(fork, stream)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(side, fork, 0)) != hipSuccess) return e;
+  if (nside > 0) {
+    if ((e = hipEventRecord(ss->fork, stream)) != hipSuccess) return e;
+    for (int i = 0; i < nside; ++i)
+      if ((e = hipStreamWaitEvent(ss->side[i], ss->fork, 0)) != hipSuccess) return e;
   }
   for (size_t j = 0; j < launches.size(); ++j) {
     const GroupLaunch& g = launches[j];
+    const int q = nside > 0 ? static_cast<int>(j % static_cast<size_t>(nside + 1)) : 0;
     e = g.fn(dev + g.items_off, reinterpret_cast<const BlockMap*>(dev + g.map_off), g.nblocks,
-             split && j % 2 == 1 ? side : stream);
+             q == 0 ? stream : ss->side[q - 1]);
     if (e != hipSuccess) return e;
   }
-  if (split) {
-    if ((e = hipEventRecord(join, side)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(stream, join, 0)) != hipSuccess) return e;
+  for (int i = 0; i < nside; ++i) {
+    if ((e = hipEventRecord(ss->join[i], ss->side[i])) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(stream, ss->join[i], 0)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -114,19 +155,19 @@ s5d_status check_disjoint(const std::vector<std::pair<uintptr_t, uintptr_t>>& ra
 }  // namespace s5d
 
 struct s5d_batch {
-  struct Boundary {
-    const void* src;
-    void* dst;
-    int elem, ndim, r;
-    int64_t padded[3];
-  };
-  std::vector<Boundary> boundaries;
+  // boundary copies of every grid with work: one launch over a device table
+  // of HaloItems at byte offset halo_off of the device blob
+  int32_t n_halo = 0;
+  int64_t halo_max_cells = 0;
+  size_t halo_off = 0;
   std::vector<std::vector<s5d::GroupLaunch>> steps;
   std::vector<int32_t> result_index;
+  // device coefficient tables of the plans (direct kernels read them through
+  // the batch items); held here because plans may be destroyed after creation
+  std::vector<std::shared_ptr<void>> coef_tables;
   unsigned char* dev = nullptr;
   int device = 0;
-  hipStream_t side = nullptr;  // second stream for steps of several kernel variants
-  hipEvent_t fork = nullptr, join = nullptr;
+  s5d::StepStreams ss;  // side streams for steps of several kernel variants
   bool graph = false;
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -135,12 +176,15 @@ struct s5d_batch {
 namespace {
 
 hipError_t enqueue_batch(const s5d_batch* b, hipStream_t st) {
-  for (const s5d_batch::Boundary& h : b->boundaries) {
-    const hipError_t e = s5d::launch_halo_copy(h.src, h.dst, h.elem, h.ndim, h.padded, h.r, st);
+  constexpr int kMaxHaloItems = 65535;  // grid y-dimension of the boundary-copy launch
+  const s5d::HaloItem* halo = reinterpret_cast<const s5d::HaloItem*>(b->dev + b->halo_off);
+  for (int32_t i = 0; i < b->n_halo; i += kMaxHaloItems) {
+    const hipError_t e = s5d::launch_halo_copy_batch(halo + i, std::min(kMaxHaloItems, b->n_halo - i),
+                                                     b->halo_max_cells, st);
     if (e != hipSuccess) return e;
   }
   for (const auto& step : b->steps) {
-    const hipError_t e = s5d::enqueue_step(step, b->dev, st, b->side, b->fork, b->join);
+    const hipError_t e = s5d::enqueue_step(step, b->dev, st, &b->ss);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -151,9 +195,7 @@ void release(s5d_batch* b) {
   if (b->exec || b->dev) (void)hipDeviceSynchronize();
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
-  if (b->side) (void)hipStreamDestroy(b->side);
-  if (b->fork) (void)hipEventDestroy(b->fork);
-  if (b->join) (void)hipEventDestroy(b->join);
+  b->ss.destroy();
   if (b->dev) (void)hipFree(b->dev);
   (void)hipGetLastError();
   delete b;
@@ -193,18 +235,28 @@ s5d_status s5d_batch_create(const s5d_plan* const* plans, void* const* buf0, voi
   std::vector<std::vector<int>> rounds(static_cast<size_t>(n));
   size_t kmax = 0;
   try {
+    std::vector<s5d::HaloItem> halos;
     b->result_index.resize(static_cast<size_t>(n));
     for (int32_t g = 0; g < n; ++g) {
       const s5d_plan* p = plans[g];
       b->result_index[g] = static_cast<int32_t>(p->d.steps % 2);
+      if (p->dcoef) b->coef_tables.push_back(p->dcoef);
       rounds[g] = s5d::plan_rounds(p);
       kmax = std::max(kmax, rounds[g].size());
       if (!rounds[g].empty()) {
-        s5d_batch::Boundary h{buf0[g], buf1[g], p->elem, p->d.ndim, p->d.radius, {0, 0, 0}};
-        for (int a = 0; a < 3; ++a) h.padded[a] = p->padded[a];
-        b->boundaries.push_back(h);
+        s5d::HaloItem h;
+        h.src = buf0[g];
+        h.dst = buf1[g];
+        h.P0 = p->padded[0];
+        h.P1 = p->padded[1];
+        h.P2 = p->d.ndim == 3 ? p->padded[2] : 1;
+        h.r = p->d.radius;
+        h.elem = p->elem;
+        halos.push_back(h);
+        b->halo_max_cells = std::max(b->halo_max_cells, s5d::halo_cells(p->d.ndim, p->padded, p->d.radius));
       }
     }
+    b->n_halo = static_cast<int32_t>(halos.size());
     // Each grid shares the machine with all the others (launches of different
     // kernel variants overlap on two streams): its stream blocks are chosen
     // for its fraction of the batch's cell-updates, which gives the small
@@ -222,6 +274,11 @@ s5d_status s5d_batch_create(const s5d_plan* const* plans, void* const* buf0, voi
       if (!rounds[g].empty() && total_work > 0)
         chunks[g] = s5d::shared_chunk(plans[g], plans[g]->tun.bt, work[g] / total_work);
     std::vector<unsigned char> blob;
+    if (!halos.empty()) {
+      b->halo_off = 0;
+      blob.resize(halos.size() * sizeof(s5d::HaloItem));
+      std::memcpy(blob.data(), halos.data(), blob.size());
+    }
     b->steps.resize(kmax);
     for (size_t k = 0; k < kmax; ++k) {
       std::vector<s5d::RoundItem> items;
@@ -252,15 +309,13 @@ s5d_status s5d_batch_create(const s5d_plan* const* plans, void* const* buf0, voi
         release(b);
         return device_fail(e, "upload of the batch tables");
       }
-      bool multi = false;
-      for (const auto& step : b->steps) multi = multi || step.size() >= 2;
-      if (multi) {
-        e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
+      size_t widest = 1;
+      for (const auto& step : b->steps) widest = std::max(widest, step.size());
+      if (widest >= 2) {
+        e = b->ss.create(static_cast<int>(std::min<size_t>(widest - 1, s5d::kMaxSideStreams)));
         if (e != hipSuccess) {
           release(b);
-          return device_fail(e, "side stream of the batch");
+          return device_fail(e, "side streams of the batch");
         }
       }
     }
@@ -279,7 +334,7 @@ s5d_status s5d_batch_run(s5d_batch* batch, void* stream, int32_t* result_index) 
   (void)hipGetLastError();
   if (result_index)
     for (size_t g = 0; g < batch->result_index.size(); ++g) result_index[g] = batch->result_index[g];
-  if (batch->boundaries.empty()) return S5D_OK;
+  if (batch->n_halo == 0) return S5D_OK;
   if (!batch->graph) {
     const hipError_t e = enqueue_batch(batch, st);
     return e == hipSuccess ? S5D_OK : device_fail(e, "batched launch");
@@ -315,7 +370,7 @@ s5d_status s5d_batch_run(s5d_batch* batch, void* stream, int32_t* result_index) 
 s5d_status s5d_batch_query(const s5d_batch* batch, int32_t* n_launches, int32_t* n_round_steps) {
   s5d::clear_error();
   if (!batch) return fail(S5D_EINVAL, "batch is NULL");
-  int32_t nl = static_cast<int32_t>(batch->boundaries.size());
+  int32_t nl = (batch->n_halo + 65534) / 65535;
   for (const auto& s : batch->steps) nl += static_cast<int32_t>(s.size());
   if (n_launches) *n_launches = nl;
   if (n_round_steps) *n_round_steps = static_cast<int32_t>(batch->steps.size());

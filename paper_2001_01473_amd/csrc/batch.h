@@ -35,13 +35,26 @@ struct GroupLaunch {
 s5d_status build_step(const std::vector<RoundItem>& items, std::vector<unsigned char>& blob,
                       std::vector<GroupLaunch>& out);
 
-// Enqueue the launches of a step whose table was uploaded to `dev`.  With a
-// side stream and two events, a step of several launches (kernel variants)
-// forks: every other launch goes to the side stream, so launches of different
-// variants overlap (they touch different grids), and the step joins back into
-// `stream` before the next one.
+// Streams a step's launches spread over: the caller's stream plus up to
+// kMaxSideStreams side streams that fork from it and join back into it.
+constexpr int kMaxSideStreams = 3;
+struct StepStreams {
+  int n_side = 0;
+  hipStream_t side[kMaxSideStreams] = {nullptr, nullptr, nullptr};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kMaxSideStreams] = {nullptr, nullptr, nullptr};
+  // create n_side non-blocking side streams and their events (n_side <= kMaxSideStreams)
+  hipError_t create(int n_side);
+  void destroy();
+};
+
+// Enqueue the launches of a step whose table was uploaded to `dev`.  With
+// side streams, a step of several launches (kernel variants, which touch
+// different grids) forks: launch j goes to stream j mod (1 + n_side), so the
+// variants overlap on the device, and the step joins back into `stream`
+// before the next one.
 hipError_t enqueue_step(const std::vector<GroupLaunch>& launches, const unsigned char* dev, hipStream_t stream,
-                        hipStream_t side = nullptr, hipEvent_t fork = nullptr, hipEvent_t join = nullptr);
+                        const StepStreams* ss = nullptr);
 
 // EINVAL if any two [begin, end) byte ranges overlap.
 s5d_status check_disjoint(const std::vector<std::pair<uintptr_t, uintptr_t>>& ranges);

@@ -20,6 +20,7 @@ struct s5d_plan {
   int64_t bytes;
   int elem;
   int kind;                  // kernel kind: KIND_F32, KIND_F64 or KIND_F32_COMP
+  int expr = 0;              // S5D_EXPR_*
   bool direct = false;       // direct kernels (one step per launch) instead of blocked ones
   bool chunk_auto = false;   // stream_chunk was chosen by the library (not asked for)
   int64_t slots = 0;         // 2D: resident waves of the plan's variant on the whole device
@@ -42,8 +43,10 @@ void clear_error();
 // number of rounds has the parity of T, so the result is in buffer T % 2.
 std::vector<int> plan_rounds(const s5d_plan* p);
 
-// Launch one round of bt fused steps of plan p from src into dst.
-hipError_t launch_round(const s5d_plan* p, int bt, const void* src, void* dst, hipStream_t stream);
+// Launch one round of bt fused steps of plan p from src into dst (fields:
+// the per-cell weights of a variable-coefficient plan, else null).
+hipError_t launch_round(const s5d_plan* p, int bt, const void* src, void* dst, hipStream_t stream,
+                        const void* fields = nullptr);
 
 // The batched-launch hooks of the kernel that runs a round of bt steps of p.
 struct BatchHooks {

@@ -112,6 +112,11 @@ __device__ __forceinline__ S uniform_copy(const S& src) {
   return out;
 }
 
+// Correctly rounded square roots (the build keeps HIP's IEEE-exact division
+// and square root; no fast-math).
+__device__ __forceinline__ float ieee_sqrt(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double ieee_sqrt(double x) { return __builtin_sqrt(x); }
+
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -209,6 +214,18 @@ struct Accum<float, 1> {
     return s + q;
   }
 };
+
+// The value a finished output cell takes: its sum, or (EXPR_DIV) its sum
+// divided by the last coefficient c0 -- one correctly rounded division.
+template <int EXPR, typename T, typename Pack>
+__device__ __forceinline__ T finish(T sum, const Pack& cf) {
+  if constexpr (EXPR == EXPR_DIV) {
+    constexpr int n = sizeof(cf.c) / sizeof(cf.c[0]);
+    return sum / cf.c[n - 1];
+  } else {
+    return sum;
+  }
+}
 
 // A lane's CPL consecutive cells, element-aligned, read as one vector access.
 template <typename T, int N>

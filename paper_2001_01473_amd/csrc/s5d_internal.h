@@ -12,6 +12,14 @@ constexpr int npts(int ndim, int r, bool box) {
              : 2 * r * ndim + 1;
 }
 
+// Expressions of the blocked kernels: the plain weighted sum, or the weighted
+// sum divided by one constant c0 (AN5D Table 3: j2d5pt, j2d9pt, j2d9pt-gol,
+// j3d27pt), which travels after the weights.
+enum { EXPR_LINEAR = 0, EXPR_DIV = 1, EXPR_GRADIENT = 2, EXPR_VARCOEF = 3 };
+constexpr int ncoef(int ndim, int r, bool box, int expr) {
+  return npts(ndim, r, box) + (expr == EXPR_DIV ? 1 : 0);
+}
+
 // Columns of overlap on the left and right of a tile (the last axis): at
 // least bt*r each (the valid width shrinks by r per side and level), chosen so
 // that the tile's first column and the compute width are multiples of
@@ -49,6 +57,7 @@ struct Round2D {
   const double* coeffs;  // host, canonical order
   const void* dcoef;     // device copy in the working type (direct kernels)
   hipStream_t stream;
+  const void* fields = nullptr;  // per-cell weights (variable-coefficient sweeps)
 };
 
 // Stream blocks of a 2D launch, laid out for the XCDs.  Workgroups are
@@ -148,6 +157,7 @@ enum { KIND_F32 = 0, KIND_F64 = 1, KIND_F32_COMP = 2 };
 
 struct Entry2D {
   int dtype;   // kernel kind: KIND_F32, KIND_F64 or KIND_F32_COMP
+  int expr;    // EXPR_LINEAR or EXPR_DIV (window kernels: EXPR_GRADIENT, EXPR_VARCOEF)
   int box;     // 0 = star, 1 = box
   int r;
   int cpl;
@@ -193,6 +203,7 @@ struct Kernel3D {
 
 struct Entry3D {
   int dtype;  // kernel kind, as for Entry2D
+  int expr;   // EXPR_LINEAR or EXPR_DIV
   int box, r, cpl, m, nw, bt;
   Kernel3D (*make)();
 };
@@ -208,6 +219,18 @@ Kernel3D direct_kernel3d(int kind, int r, bool box);
 // Copy the boundary cells (width r on every face) of a padded grid.
 hipError_t launch_halo_copy(const void* src, void* dst, int elem_bytes, int ndim,
                             const int64_t* padded, int r, hipStream_t stream);
+
+// The boundary copies of many grids in one launch: a device table of n items
+// (at most 65535); max_cells = the largest halo_cells() among them.
+struct HaloItem {
+  const void* src;
+  void* dst;
+  int64_t P0, P1, P2;  // padded extents (P2 = 1 for 2D grids)
+  int32_t r;           // boundary width
+  int32_t elem;        // bytes per cell: 4 or 8
+};
+int64_t halo_cells(int ndim, const int64_t* padded, int r);
+hipError_t launch_halo_copy_batch(const HaloItem* items, int n, int64_t max_cells, hipStream_t stream);
 
 constexpr int kWavesPerBlock = 4;
 

@@ -41,8 +41,11 @@ struct Request {
   int64_t id = 0;
   s5d_plan plan;
   const void* init = nullptr;
+  hipEvent_t init_ev = nullptr;  // recorded after the copy of init; null once that copy is known done
   bool keep = false;
+  bool cancel = false;           // cancellation asked for while running
   int32_t state = S5D_REQ_QUEUED;
+  s5d_status status = S5D_OK;    // why a FAILED request failed
   double t_arrival = 0, t_admit = -1, t_done = -1;
   std::vector<int> rounds;
   size_t next = 0;
@@ -71,8 +74,7 @@ struct Finishing {
 struct s5d_server {
   s5d_server_config cfg;
   hipStream_t stream = nullptr;
-  hipStream_t side = nullptr;  // second stream: launches of different kernel variants overlap
-  hipEvent_t fork = nullptr, join = nullptr;
+  s5d::StepStreams ss;  // side streams: launches of different kernel variants overlap
   hipEvent_t base = nullptr;
   std::chrono::steady_clock::time_point t0;
   std::unordered_map<int64_t, std::unique_ptr<Request>> reqs;
@@ -83,7 +85,8 @@ struct s5d_server {
   Slot slots[kSlots];
   int64_t next_id = 1;
   int64_t used = 0, peak = 0;
-  int64_t ticks = 0, launches = 0, done = 0, updates_done = 0;
+  int64_t ticks = 0, launches = 0, done = 0, failed = 0, updates_done = 0;
+  int64_t admissions = 0, work_ticks = 0;  // counters of the fault-injection knobs
   double first_arrival = -1, last_done = -1;
   std::vector<double> latencies;
 };
@@ -108,11 +111,34 @@ s5d_status take_event(s5d_server* s, hipEvent_t* ev) {
 }
 
 void release_buffers(s5d_server* s, Request* r) {
+  bool held = false;
   for (void*& b : r->buf) {
     if (b) (void)hipFreeAsync(b, s->stream);  // stream-ordered: after the request's last use
+    held = held || b;
     b = nullptr;
   }
-  s->used -= r->bytes2;
+  if (held) s->used -= r->bytes2;
+}
+
+// Has the copy out of the request's init been completed on the device?
+// (Returns the event to the pool once it has.)
+bool init_released(const s5d_server* cs, Request* r) {
+  if (!r->init_ev) return true;
+  const hipError_t q = hipEventQuery(r->init_ev);
+  if (q == hipErrorNotReady) return false;
+  (void)hipGetLastError();
+  const_cast<s5d_server*>(cs)->event_pool.push_back(r->init_ev);
+  r->init_ev = nullptr;
+  return true;
+}
+
+// A request that will not run (any more): FAILED, memory returned.
+void fail_request(s5d_server* s, Request* r, s5d_status why) {
+  release_buffers(s, r);
+  r->state = S5D_REQ_FAILED;
+  r->status = why;
+  r->init = nullptr;
+  ++s->failed;
 }
 
 // Move requests whose completion event has fired to DONE.
@@ -146,15 +172,23 @@ s5d_status record_finish(s5d_server* s, const std::vector<Request*>& reqs) {
   const s5d_status st = take_event(s, &ev);
   if (st != S5D_OK) return st;
   const hipError_t e = hipEventRecord(ev, s->stream);
-  if (e != hipSuccess) return device_fail(e, "hipEventRecord");
+  if (e != hipSuccess) {
+    s->event_pool.push_back(ev);
+    return device_fail(e, "hipEventRecord");
+  }
   for (Request* r : reqs)
     if (!r->keep) release_buffers(s, r);
   s->finishing.push_back(Finishing{ev, reqs});
   return S5D_OK;
 }
 
+// Allocate the request's buffers, copy its initial grid in, copy the
+// boundary into the second buffer.  On failure nothing stays allocated and
+// the request is left for the caller to fail.
 s5d_status admit(s5d_server* s, Request* r) {
   const int64_t nb = r->plan.bytes;
+  if (s->cfg.fail_admit_every > 0 && (++s->admissions % s->cfg.fail_admit_every) == 0)
+    return fail(S5D_EDEVICE, "injected admission failure (fail_admit_every)");
   for (int i = 0; i < 2; ++i) {
     const hipError_t e = hipMallocAsync(&r->buf[i], static_cast<size_t>(nb), s->stream);
     if (e != hipSuccess) {
@@ -163,11 +197,23 @@ s5d_status admit(s5d_server* s, Request* r) {
         (void)hipFreeAsync(r->buf[0], s->stream);
         r->buf[0] = nullptr;
       }
+      (void)hipGetLastError();
       return device_fail(e, "hipMallocAsync");
     }
   }
+  s->used += r->bytes2;  // release_buffers gives it back from here on
   hipError_t e = hipMemcpyAsync(r->buf[0], r->init, static_cast<size_t>(nb), hipMemcpyDefault, s->stream);
   if (e != hipSuccess) return device_fail(e, "initial copy");
+  // init may be dropped by the caller only once this copy has run
+  hipEvent_t ev = nullptr;
+  s5d_status st = take_event(s, &ev);
+  if (st != S5D_OK) return st;
+  e = hipEventRecord(ev, s->stream);
+  if (e != hipSuccess) {
+    s->event_pool.push_back(ev);
+    return device_fail(e, "hipEventRecord");
+  }
+  r->init_ev = ev;
   r->init = nullptr;
   r->rounds = s5d::plan_rounds(&r->plan);
   if (!r->rounds.empty()) {
@@ -184,6 +230,7 @@ s5d_status grow_slot(Slot& sl, size_t need) {
   size_t cap = std::max<size_t>(need, 2 * sl.cap);
   cap = std::max<size_t>(cap, 1 << 16);
   if (sl.pending) (void)hipEventSynchronize(sl.ev);
+  sl.pending = false;
   if (sl.host) (void)hipHostFree(sl.host);
   if (sl.dev) (void)hipFree(sl.dev);
   sl.host = nullptr;
@@ -206,9 +253,11 @@ s5d_status grow_slot(Slot& sl, size_t need) {
 void destroy_server(s5d_server* s) {
   if (!s) return;
   if (s->stream) (void)hipStreamSynchronize(s->stream);
-  for (auto& kv : s->reqs)
+  for (auto& kv : s->reqs) {
     for (void* b : kv.second->buf)
       if (b) (void)hipFreeAsync(b, s->stream);
+    if (kv.second->init_ev) (void)hipEventDestroy(kv.second->init_ev);
+  }
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   for (Slot& sl : s->slots) {
     if (sl.host) (void)hipHostFree(sl.host);
@@ -218,10 +267,7 @@ void destroy_server(s5d_server* s) {
   for (Finishing& f : s->finishing) (void)hipEventDestroy(f.ev);
   for (hipEvent_t ev : s->event_pool) (void)hipEventDestroy(ev);
   if (s->base) (void)hipEventDestroy(s->base);
-  if (s->side) (void)hipStreamSynchronize(s->side);
-  if (s->side) (void)hipStreamDestroy(s->side);
-  if (s->fork) (void)hipEventDestroy(s->fork);
-  if (s->join) (void)hipEventDestroy(s->join);
+  s->ss.destroy();
   if (s->stream) (void)hipStreamDestroy(s->stream);
   (void)hipGetLastError();
   delete s;
@@ -234,6 +280,25 @@ double percentile(std::vector<double> v, double q) {
   size_t k = static_cast<size_t>(std::ceil(q * static_cast<double>(v.size())));
   k = std::min(std::max<size_t>(k, 1), v.size());
   return v[k - 1];
+}
+
+// Can every round of this plan go into a batched launch?  (Checked at
+// submission, so that a tick never meets a request it cannot launch.)
+s5d_status check_batchable(const s5d_plan* p) {
+  const std::vector<int> rounds = s5d::plan_rounds(p);
+  std::vector<int> seen;
+  static char dummy[2][16];
+  for (int bt : rounds) {
+    if (std::find(seen.begin(), seen.end(), bt) != seen.end()) continue;
+    seen.push_back(bt);
+    const s5d::BatchHooks h = s5d::batch_hooks(p, bt);
+    if (!h.launch || h.item_bytes <= 0) return fail(S5D_EUNSUPPORTED, "kernel variant without a batched entry point");
+    std::vector<unsigned char> item(static_cast<size_t>(h.item_bytes) + 16);
+    void* tmp = reinterpret_cast<void*>((reinterpret_cast<uintptr_t>(item.data()) + 15) & ~uintptr_t(15));
+    if (s5d::fill_round_item(p, bt, dummy[0], dummy[1], tmp) <= 0)
+      return fail(S5D_EUNSUPPORTED, "grid too large for one batched launch");
+  }
+  return S5D_OK;
 }
 
 }  // namespace
@@ -250,22 +315,24 @@ s5d_status s5d_server_create(const s5d_server_config* config, s5d_server** out) 
   if (config->max_running < 0) return fail(S5D_EINVAL, "max_running must be >= 0");
   if (config->rounds_per_tick < 0 || config->rounds_per_tick > 1024)
     return fail(S5D_EINVAL, "rounds_per_tick must be in 0..1024");
+  if (config->n_streams < 0 || config->n_streams > 1 + s5d::kMaxSideStreams)
+    return fail(S5D_EINVAL, "n_streams must be in 0..4");
+  if (config->fail_admit_every < 0 || config->fail_tick_every < 0)
+    return fail(S5D_EINVAL, "fault-injection periods must be >= 0");
   s5d_server* s = new (std::nothrow) s5d_server;
   if (!s) return fail(S5D_ENOMEM, "server allocation failed");
   s->cfg = *config;
+  if (s->cfg.n_streams == 0) s->cfg.n_streams = 1 + s5d::kMaxSideStreams;
   hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     s->stream = nullptr;
     destroy_server(s);
     return device_fail(e, "server stream");
   }
-  e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
-  if (e != hipSuccess) s->side = nullptr;
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->join, hipEventDisableTiming);
+  e = s->ss.create(s->cfg.n_streams - 1);
   if (e != hipSuccess) {
     destroy_server(s);
-    return device_fail(e, "server side stream");
+    return device_fail(e, "server side streams");
   }
   for (Slot& sl : s->slots) {
     e = hipEventCreate(&sl.ev);
@@ -301,6 +368,8 @@ s5d_status s5d_server_submit(s5d_server* s, const s5d_plan* plan, const void* in
   if (!s || !plan || !init) return fail(S5D_EINVAL, "server, plan and init must not be NULL");
   const int64_t bytes2 = 2 * plan->bytes;
   if (bytes2 > s->cfg.hbm_budget_bytes) return fail(S5D_EBUDGET, "request larger than the HBM budget");
+  const s5d_status bst = check_batchable(plan);
+  if (bst != S5D_OK) return bst;
   std::unique_ptr<Request> r(new (std::nothrow) Request);
   if (!r) return fail(S5D_ENOMEM, "request allocation failed");
   try {
@@ -323,22 +392,53 @@ s5d_status s5d_server_submit(s5d_server* s, const s5d_plan* plan, const void* in
   return S5D_OK;
 }
 
+s5d_status s5d_server_cancel(s5d_server* s, int64_t id) {
+  s5d::clear_error();
+  if (!s) return fail(S5D_EINVAL, "server is NULL");
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return fail(S5D_EINVAL, "unknown request id");
+  Request* r = it->second.get();
+  if (r->state == S5D_REQ_QUEUED) {
+    s->queue.erase(std::remove(s->queue.begin(), s->queue.end(), r), s->queue.end());
+    fail_request(s, r, S5D_ECANCELED);
+  } else if (r->state == S5D_REQ_RUNNING) {
+    // leaves at the start of the next tick, before any further round of it
+    r->cancel = true;
+  }
+  return S5D_OK;
+}
+
 s5d_status s5d_server_tick(s5d_server* s, int32_t* n_running, int32_t* n_queued) {
   s5d::clear_error();
   if (!s) return fail(S5D_EINVAL, "server is NULL");
   s5d_status st = retire(s);
   if (st != S5D_OK) return st;
-  // 1. admission, FIFO under the budget
+  // cancelled requests leave before this tick's rounds; their buffers are
+  // freed after the work already enqueued for them
+  {
+    std::vector<Request*> still;
+    for (Request* r : s->running) {
+      if (r->cancel)
+        fail_request(s, r, S5D_ECANCELED);
+      else
+        still.push_back(r);
+    }
+    s->running.swap(still);
+  }
+  // 1. admission, FIFO under the budget; a request whose admission fails is
+  // FAILED and the queue moves on
   std::vector<Request*> fin;
   while (!s->queue.empty()) {
     Request* r = s->queue.front();
     if (s->cfg.max_running > 0 && static_cast<int64_t>(s->running.size()) >= s->cfg.max_running) break;
     if (s->used + r->bytes2 > s->cfg.hbm_budget_bytes) break;
-    st = admit(s, r);
-    if (st != S5D_OK) return st;
-    s->used += r->bytes2;
-    s->peak = std::max(s->peak, s->used);
     s->queue.pop_front();
+    st = admit(s, r);
+    if (st != S5D_OK) {
+      fail_request(s, r, st);
+      continue;
+    }
+    s->peak = std::max(s->peak, s->used);
     if (r->rounds.empty())
       fin.push_back(r);  // zero steps: the result is the initial grid
     else
@@ -347,45 +447,56 @@ s5d_status s5d_server_tick(s5d_server* s, int32_t* n_running, int32_t* n_queued)
   // requests of zero steps finish at admission
   if (!fin.empty()) {
     st = record_finish(s, fin);
-    if (st != S5D_OK) return st;
+    if (st != S5D_OK) {
+      for (Request* r : fin) fail_request(s, r, st);
+      return st;
+    }
     fin.clear();
   }
-  // 2. one round (or a few, while few requests run) of every running request
+  // 2. one round (or a few, while few requests run) of every running request.
+  // The tick is planned on copies of the requests' round indices, which are
+  // committed only for rounds whose launches were enqueued.
   if (!s->running.empty()) {
     const int n = static_cast<int>(s->running.size());
     const int K = s->cfg.rounds_per_tick > 0
                       ? s->cfg.rounds_per_tick
                       : std::min(kMaxRoundsPerTick, std::max(1, (kTargetLaunches + n - 1) / n));
+    std::vector<Request*> act = s->running;
+    std::vector<size_t> nx(act.size());
+    for (size_t i = 0; i < act.size(); ++i) nx[i] = act[i]->next;
     std::vector<unsigned char> blob;
     std::vector<std::vector<s5d::GroupLaunch>> steps;
+    std::vector<std::vector<size_t>> in_step;   // indices into act of the requests of step j
     std::vector<std::vector<Request*>> fin_after;  // requests whose last round is in step j
-    for (int j = 0; j < K && !s->running.empty(); ++j) {
-      // as in a batch: each request's stream blocks are chosen for its share
-      // of the step (its fraction of the step's cell-updates; the launches of
-      // a step overlap on two streams); results do not depend on the block
-      // length
-      double step_work = 0;
-      for (Request* r : s->running) step_work += static_cast<double>(r->rounds[r->next]) * cells_of(r);
-      std::vector<s5d::RoundItem> items;
-      items.reserve(s->running.size());
-      for (Request* r : s->running) {
-        const size_t k = r->next++;
-        const int bt = r->rounds[k];
-        const int chunk = step_work > 0 ? s5d::shared_chunk(&r->plan, bt, bt * cells_of(r) / step_work) : 0;
-        items.push_back(s5d::RoundItem{&r->plan, bt, r->buf[k % 2], r->buf[(k + 1) % 2], chunk});
+    try {
+      for (int j = 0; j < K; ++j) {
+        // as in a batch: each request's stream blocks are chosen for its share
+        // of the step (its fraction of the step's cell-updates; the launches
+        // of a step overlap on several streams); results do not depend on the
+        // block length
+        double step_work = 0;
+        for (size_t i = 0; i < act.size(); ++i)
+          if (nx[i] < act[i]->rounds.size()) step_work += static_cast<double>(act[i]->rounds[nx[i]]) * cells_of(act[i]);
+        if (step_work <= 0) break;
+        std::vector<s5d::RoundItem> items;
+        in_step.emplace_back();
+        fin_after.emplace_back();
+        for (size_t i = 0; i < act.size(); ++i) {
+          Request* r = act[i];
+          if (nx[i] >= r->rounds.size()) continue;
+          const size_t k = nx[i]++;
+          const int bt = r->rounds[k];
+          const int chunk = s5d::shared_chunk(&r->plan, bt, bt * cells_of(r) / step_work);
+          items.push_back(s5d::RoundItem{&r->plan, bt, r->buf[k % 2], r->buf[(k + 1) % 2], chunk});
+          in_step.back().push_back(i);
+          if (nx[i] == r->rounds.size()) fin_after.back().push_back(r);
+        }
+        steps.emplace_back();
+        st = s5d::build_step(items, blob, steps.back());
+        if (st != S5D_OK) return st;  // nothing enqueued, nothing committed
       }
-      steps.emplace_back();
-      st = s5d::build_step(items, blob, steps.back());
-      if (st != S5D_OK) return st;
-      fin_after.emplace_back();
-      std::vector<Request*> still;
-      for (Request* r : s->running) {
-        if (r->next == r->rounds.size())
-          fin_after.back().push_back(r);
-        else
-          still.push_back(r);
-      }
-      s->running.swap(still);
+    } catch (const std::bad_alloc&) {
+      return fail(S5D_ENOMEM, "host allocation failed while planning a tick");
     }
     Slot& sl = s->slots[s->ticks % kSlots];
     if (sl.pending) {
@@ -398,19 +509,56 @@ s5d_status s5d_server_tick(s5d_server* s, int32_t* n_running, int32_t* n_queued)
     std::memcpy(sl.host, blob.data(), blob.size());
     hipError_t e = hipMemcpyAsync(sl.dev, sl.host, blob.size(), hipMemcpyHostToDevice, s->stream);
     if (e != hipSuccess) return device_fail(e, "tick table upload");
-    for (size_t j = 0; j < steps.size(); ++j) {
-      e = s5d::enqueue_step(steps[j], sl.dev, s->stream, s->side, s->fork, s->join);
-      if (e != hipSuccess) return device_fail(e, "tick launch");
-      s->launches += static_cast<int64_t>(steps[j].size());
-      if (!fin_after[j].empty()) {
-        st = record_finish(s, fin_after[j]);
-        if (st != S5D_OK) return st;
-      }
-    }
-    e = hipEventRecord(sl.ev, s->stream);
-    if (e != hipSuccess) return device_fail(e, "hipEventRecord");
+    // the staging slot is busy from here on, whatever happens below
+    (void)hipEventRecord(sl.ev, s->stream);
     sl.pending = true;
     ++s->ticks;
+    const bool inject = s->cfg.fail_tick_every > 0 && (++s->work_ticks % s->cfg.fail_tick_every) == 0;
+    size_t j_bad = steps.size();  // first step whose launches did not all go out
+    s5d_status bad = S5D_OK;
+    for (size_t j = 0; j < steps.size(); ++j) {
+      if (inject && j + 1 == steps.size()) {
+        bad = fail(S5D_EDEVICE, "injected launch failure (fail_tick_every)");
+        j_bad = j;
+        break;
+      }
+      e = s5d::enqueue_step(steps[j], sl.dev, s->stream, &s->ss);
+      if (e != hipSuccess) {
+        bad = device_fail(e, "tick launch");
+        j_bad = j;
+        break;
+      }
+      s->launches += static_cast<int64_t>(steps[j].size());
+      // requests whose last round is in step j complete when it does (a
+      // request that ends here has no round in a later step, so a failure
+      // further on cannot touch it)
+      if (!fin_after[j].empty()) {
+        const s5d_status fst = record_finish(s, fin_after[j]);
+        if (fst != S5D_OK) {
+          for (Request* r : fin_after[j]) fail_request(s, r, fst);
+          bad = fst;
+        }
+      }
+    }
+    if (j_bad == 0) return bad;  // nothing of this tick was enqueued: no round index moves
+    // commit the round indices of the launched steps; a request with a round
+    // in a step that was not (wholly) launched is FAILED
+    std::vector<char> hit(act.size(), 0);
+    for (size_t j = j_bad; j < steps.size(); ++j)
+      for (size_t i : in_step[j]) hit[i] = 1;
+    std::vector<Request*> still;
+    for (size_t i = 0; i < act.size(); ++i) {
+      Request* r = act[i];
+      if (r->state != S5D_REQ_RUNNING) continue;  // failed above
+      if (hit[i]) {
+        fail_request(s, r, bad);
+        continue;
+      }
+      r->next = nx[i];
+      if (r->next < r->rounds.size()) still.push_back(r);
+    }
+    s->running.swap(still);
+    if (bad != S5D_OK) return bad;
   }
   if (n_running) *n_running = static_cast<int32_t>(s->running.size());
   if (n_queued) *n_queued = static_cast<int32_t>(s->queue.size());
@@ -431,14 +579,16 @@ s5d_status s5d_server_request(const s5d_server* s, int64_t id, s5d_request_info*
   if (info->struct_size < sizeof(s5d_request_info)) return fail(S5D_EINVAL, "info->struct_size too small");
   auto it = s->reqs.find(id);
   if (it == s->reqs.end()) return fail(S5D_EINVAL, "unknown request id");
-  const Request* r = it->second.get();
+  Request* r = it->second.get();
   info->state = r->state;
+  info->status = r->status;
   info->result_index = static_cast<int32_t>(r->plan.d.steps % 2);
   info->updates = r->updates;
   info->t_arrival = r->t_arrival;
   info->t_admit = r->t_admit;
   info->t_done = r->t_done;
   info->rounds_done = static_cast<int64_t>(r->next);
+  info->init_in_use = (r->state == S5D_REQ_QUEUED || !init_released(s, r)) ? 1 : 0;
   return S5D_OK;
 }
 
@@ -468,6 +618,7 @@ s5d_status s5d_server_get_stats(const s5d_server* s, s5d_server_stats* out) {
   out->queued = static_cast<int64_t>(s->queue.size());
   out->running = static_cast<int64_t>(s->running.size());
   out->done = s->done;
+  out->failed = s->failed;
   out->bytes_in_use = s->used;
   out->bytes_peak = s->peak;
   out->ticks = s->ticks;

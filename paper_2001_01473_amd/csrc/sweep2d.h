@@ -68,8 +68,8 @@ constexpr bool folded_coef2d(int ci) {
   return BOX ? ci % (2 * R + 1) != R : (ci >= R && ci <= 3 * R && ci != 2 * R);
 }
 
-template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR, bool EDGE>
-__device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPack<T, npts(2, R, BOX)>& cf,
+template <typename T, int ACC, int EXPR, int R, bool BOX, int BT, int CPL, int NR, bool EDGE>
+__device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPack<T, ncoef(2, R, BOX, EXPR)>& cf,
                                              int lane, int tile, int row_a, int row_b,
                                              EdgeStash<T, R, BT, CPL>* stash) {
   constexpr int NA = 2 * R;         // pending output rows per level
@@ -232,7 +232,7 @@ __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPac
         sfor<CPL>([&](auto K) S5D_INL {
           Accum<T, ACC> v = A[so][K];
           add_row(ic<R>{}, v, K, std::false_type{});
-          out[K] = v.value();
+          out[K] = finish<EXPR>(v.value(), cf);
         });
         // 2. output p+R starts in the freed slot (d0 = -R)
         sfor<CPL>([&](auto K) S5D_INL { add_row(ic<-R>{}, A[so][K], K, std::true_type{}); });
@@ -284,8 +284,8 @@ __device__ __forceinline__ void sweep2d_body(const Sweep2DArgs& a, const CoefPac
 // Workgroup lb of one grid's launch: kWavesPerBlock waves, one tile each, of
 // band lb % nb (with 8 bands, the XCD the workgroup runs on in a launch of
 // its own).
-template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
-__device__ __forceinline__ void sweep2d_block(const Sweep2DArgs& a, const CoefPack<T, npts(2, R, BOX)>& cf, int lb,
+template <typename T, int ACC, int EXPR, int R, bool BOX, int BT, int CPL, int NR>
+__device__ __forceinline__ void sweep2d_block(const Sweep2DArgs& a, const CoefPack<T, ncoef(2, R, BOX, EXPR)>& cf, int lb,
                                               EdgeStash<T, R, BT, CPL>* stash) {
   constexpr int W = 64 * CPL;
   constexpr int LO = overlap_left(BT, R, sizeof(T));
@@ -308,16 +308,16 @@ __device__ __forceinline__ void sweep2d_block(const Sweep2DArgs& a, const CoefPa
   const bool edge = col0 < 0 || col0 + W > P1 || row_a - (BT - 1) * R < R ||
                     row_b + (BT - 1) * R > a.I0 + R;
   if (edge)
-    sweep2d_body<T, ACC, R, BOX, BT, CPL, NR, true>(a, cf, lane, tile, row_a, row_b, &stash[wib]);
+    sweep2d_body<T, ACC, EXPR, R, BOX, BT, CPL, NR, true>(a, cf, lane, tile, row_a, row_b, &stash[wib]);
   else
-    sweep2d_body<T, ACC, R, BOX, BT, CPL, NR, false>(a, cf, lane, tile, row_a, row_b, &stash[wib]);
+    sweep2d_body<T, ACC, EXPR, R, BOX, BT, CPL, NR, false>(a, cf, lane, tile, row_a, row_b, &stash[wib]);
 }
 
-template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
+template <typename T, int ACC, int EXPR, int R, bool BOX, int BT, int CPL, int NR>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void sweep2d_kernel(Sweep2DArgs a,
-                                                                    CoefPack<T, npts(2, R, BOX)> cf) {
+                                                                    CoefPack<T, ncoef(2, R, BOX, EXPR)> cf) {
   __shared__ EdgeStash<T, R, BT, CPL> stash[kWavesPerBlock];
-  sweep2d_block<T, ACC, R, BOX, BT, CPL, NR>(a, cf, blockIdx.x, stash);
+  sweep2d_block<T, ACC, EXPR, R, BOX, BT, CPL, NR>(a, cf, blockIdx.x, stash);
 }
 
 // One grid of a batched launch: its geometry and coefficients.
@@ -330,20 +330,20 @@ struct alignas(16) Item2D {
 // Batched launch: workgroup b runs workgroup map[b].block of grid map[b].item.
 // Item and map are read once per wave with scalar loads (uniform addresses)
 // and copied into registers before the sweep starts.
-template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
+template <typename T, int ACC, int EXPR, int R, bool BOX, int BT, int CPL, int NR>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void sweep2d_batch_kernel(
-    const Item2D<T, npts(2, R, BOX)>* __restrict__ items, const BlockMap* __restrict__ map) {
+    const Item2D<T, ncoef(2, R, BOX, EXPR)>* __restrict__ items, const BlockMap* __restrict__ map) {
   __shared__ EdgeStash<T, R, BT, CPL> stash[kWavesPerBlock];
   const BlockMap m = map[xcd_logical_block(blockIdx.x, gridDim.x)];
-  const Item2D<T, npts(2, R, BOX)>& it = items[__builtin_amdgcn_readfirstlane(m.item)];
+  const Item2D<T, ncoef(2, R, BOX, EXPR)>& it = items[__builtin_amdgcn_readfirstlane(m.item)];
   const Sweep2DArgs a = uniform_copy(it.a);
-  const CoefPack<T, npts(2, R, BOX)> cf = uniform_copy(it.cf);
-  sweep2d_block<T, ACC, R, BOX, BT, CPL, NR>(a, cf, __builtin_amdgcn_readfirstlane(m.block), stash);
+  const CoefPack<T, ncoef(2, R, BOX, EXPR)> cf = uniform_copy(it.cf);
+  sweep2d_block<T, ACC, EXPR, R, BOX, BT, CPL, NR>(a, cf, __builtin_amdgcn_readfirstlane(m.block), stash);
 }
 
-template <typename T, int R, bool BOX, int BT, int CPL>
-Sweep2DArgs make_args2d(const Round2D& rd, CoefPack<T, npts(2, R, BOX)>& cf) {
-  constexpr int NP = npts(2, R, BOX);
+template <typename T, int EXPR, int R, bool BOX, int BT, int CPL>
+Sweep2DArgs make_args2d(const Round2D& rd, CoefPack<T, ncoef(2, R, BOX, EXPR)>& cf) {
+  constexpr int NP = ncoef(2, R, BOX, EXPR);  // the divisor c0 last for EXPR_DIV
   constexpr int C = compute_width(64 * CPL, BT, R, sizeof(T));
   for (int k = 0; k < NP; ++k) cf.c[k] = static_cast<T>(rd.coeffs[k]);
   Sweep2DArgs a;
@@ -363,52 +363,52 @@ inline int blocks2d(const Sweep2DArgs& a) {
   return a.g.nb * ((a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock);
 }
 
-template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
+template <typename T, int ACC, int EXPR, int R, bool BOX, int BT, int CPL, int NR>
 hipError_t launch_sweep2d(const Round2D& rd) {
-  CoefPack<T, npts(2, R, BOX)> cf;
-  const Sweep2DArgs a = make_args2d<T, R, BOX, BT, CPL>(rd, cf);
+  CoefPack<T, ncoef(2, R, BOX, EXPR)> cf;
+  const Sweep2DArgs a = make_args2d<T, EXPR, R, BOX, BT, CPL>(rd, cf);
   if (a.nwaves == 0) return hipErrorInvalidConfiguration;
   const int nblk = blocks2d(a);
-  hipLaunchKernelGGL((sweep2d_kernel<T, ACC, R, BOX, BT, CPL, NR>), dim3(nblk), dim3(64 * kWavesPerBlock), 0,
+  hipLaunchKernelGGL((sweep2d_kernel<T, ACC, EXPR, R, BOX, BT, CPL, NR>), dim3(nblk), dim3(64 * kWavesPerBlock), 0,
                      rd.stream, a, cf);
   return hipGetLastError();
 }
 
-template <typename T, int R, bool BOX, int BT, int CPL>
+template <typename T, int EXPR, int R, bool BOX, int BT, int CPL>
 int fill_item2d(void* item, const Round2D& rd) {
-  Item2D<T, npts(2, R, BOX)> it;
-  it.a = make_args2d<T, R, BOX, BT, CPL>(rd, it.cf);
+  Item2D<T, ncoef(2, R, BOX, EXPR)> it;
+  it.a = make_args2d<T, EXPR, R, BOX, BT, CPL>(rd, it.cf);
   __builtin_memcpy(item, &it, sizeof(it));
   return blocks2d(it.a);
 }
 
-template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
+template <typename T, int ACC, int EXPR, int R, bool BOX, int BT, int CPL, int NR>
 hipError_t launch_batch2d(const void* items, const BlockMap* map, int nblocks, hipStream_t stream) {
-  hipLaunchKernelGGL((sweep2d_batch_kernel<T, ACC, R, BOX, BT, CPL, NR>), dim3(nblocks),
+  hipLaunchKernelGGL((sweep2d_batch_kernel<T, ACC, EXPR, R, BOX, BT, CPL, NR>), dim3(nblocks),
                      dim3(64 * kWavesPerBlock), 0, stream,
-                     static_cast<const Item2D<T, npts(2, R, BOX)>*>(items), map);
+                     static_cast<const Item2D<T, ncoef(2, R, BOX, EXPR)>*>(items), map);
   return hipGetLastError();
 }
 
-template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
+template <typename T, int ACC, int EXPR, int R, bool BOX, int BT, int CPL, int NR>
 int occupancy_sweep2d() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep2d_kernel<T, ACC, R, BOX, BT, CPL, NR>,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep2d_kernel<T, ACC, EXPR, R, BOX, BT, CPL, NR>,
                                                    64 * kWavesPerBlock, 0) != hipSuccess)
     return 0;
   return nb;
 }
 
-template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int NR>
+template <typename T, int ACC, int EXPR, int R, bool BOX, int BT, int CPL, int NR>
 Kernel2D make_kernel2d() {
-  return Kernel2D{&launch_sweep2d<T, ACC, R, BOX, BT, CPL, NR>,
-                  &occupancy_sweep2d<T, ACC, R, BOX, BT, CPL, NR>,
+  return Kernel2D{&launch_sweep2d<T, ACC, EXPR, R, BOX, BT, CPL, NR>,
+                  &occupancy_sweep2d<T, ACC, EXPR, R, BOX, BT, CPL, NR>,
                   CPL,
                   BT,
                   64 * CPL,
-                  &fill_item2d<T, R, BOX, BT, CPL>,
-                  &launch_batch2d<T, ACC, R, BOX, BT, CPL, NR>,
-                  static_cast<int>(sizeof(Item2D<T, npts(2, R, BOX)>))};
+                  &fill_item2d<T, EXPR, R, BOX, BT, CPL>,
+                  &launch_batch2d<T, ACC, EXPR, R, BOX, BT, CPL, NR>,
+                  static_cast<int>(sizeof(Item2D<T, ncoef(2, R, BOX, EXPR)>))};
 }
 
 }  // namespace s5d

@@ -30,8 +30,8 @@
 
 namespace s5d {
 
-template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int M, int NW, int NR, bool EDGE>
-__device__ __forceinline__ void sweep3d_body(const Sweep3DArgs& a, const CoefPack<T, npts(3, R, BOX)>& cf,
+template <typename T, int ACC, int EXPR, int R, bool BOX, int BT, int CPL, int M, int NW, int NR, bool EDGE>
+__device__ __forceinline__ void sweep3d_body(const Sweep3DArgs& a, const CoefPack<T, ncoef(3, R, BOX, EXPR)>& cf,
                                              int w, int lane, int t1, int t2, int chunk,
                                              T (*xbuf)[NW][2 * R][64 * CPL]) {
   static_assert(R <= M, "an edge-row exchange reaches one neighbouring wave only");
@@ -205,7 +205,7 @@ __device__ __forceinline__ void sweep3d_body(const Sweep3DArgs& a, const CoefPac
           sfor<CPL>([&](auto K) S5D_INL {
             Accum<T, ACC> v = A[so][MI][K];
             add_plane(ic<R>{}, v, MI, K, std::false_type{});
-            out[MI][K] = v.value();
+            out[MI][K] = finish<EXPR>(v.value(), cf);
           });
         });
         sfor<M>([&](auto MI) S5D_INL {
@@ -255,8 +255,8 @@ __device__ __forceinline__ void sweep3d_body(const Sweep3DArgs& a, const CoefPac
 }
 
 // Workgroup lb of one grid's launch: one (tile, stream block) pair.
-template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
-__device__ __forceinline__ void sweep3d_block(const Sweep3DArgs& a, const CoefPack<T, npts(3, R, BOX)>& cf, int lb,
+template <typename T, int ACC, int EXPR, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
+__device__ __forceinline__ void sweep3d_block(const Sweep3DArgs& a, const CoefPack<T, ncoef(3, R, BOX, EXPR)>& cf, int lb,
                                               T (&xbuf)[2][NW][2 * R][64 * CPL]) {
   constexpr int B1 = NW * M, B2 = 64 * CPL;
   constexpr int C1 = B1 - 2 * BT * R, C2 = compute_width(B2, BT, R, sizeof(T));
@@ -275,15 +275,15 @@ __device__ __forceinline__ void sweep3d_block(const Sweep3DArgs& a, const CoefPa
   const bool edge = row0 < 0 || row0 + B1 > P1 || col0 < 0 || col0 + B2 > P2 ||
                     pl_a - (BT - 1) * R < R || pl_b + (BT - 1) * R > a.I0 + R;
   if (edge)
-    sweep3d_body<T, ACC, R, BOX, BT, CPL, M, NW, NR, true>(a, cf, w, lane, t1, t2, chunk, xbuf);
+    sweep3d_body<T, ACC, EXPR, R, BOX, BT, CPL, M, NW, NR, true>(a, cf, w, lane, t1, t2, chunk, xbuf);
   else
-    sweep3d_body<T, ACC, R, BOX, BT, CPL, M, NW, NR, false>(a, cf, w, lane, t1, t2, chunk, xbuf);
+    sweep3d_body<T, ACC, EXPR, R, BOX, BT, CPL, M, NW, NR, false>(a, cf, w, lane, t1, t2, chunk, xbuf);
 }
 
-template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
-__global__ __launch_bounds__(64 * NW) void sweep3d_kernel(Sweep3DArgs a, CoefPack<T, npts(3, R, BOX)> cf) {
+template <typename T, int ACC, int EXPR, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
+__global__ __launch_bounds__(64 * NW) void sweep3d_kernel(Sweep3DArgs a, CoefPack<T, ncoef(3, R, BOX, EXPR)> cf) {
   __shared__ T xbuf[2][NW][2 * R][64 * CPL];
-  sweep3d_block<T, ACC, R, BOX, BT, CPL, M, NW, NR>(a, cf, xcd_logical_block(blockIdx.x, gridDim.x), xbuf);
+  sweep3d_block<T, ACC, EXPR, R, BOX, BT, CPL, M, NW, NR>(a, cf, xcd_logical_block(blockIdx.x, gridDim.x), xbuf);
 }
 
 // One grid of a batched launch: its geometry and coefficients.
@@ -294,22 +294,22 @@ struct alignas(16) Item3D {
 };
 
 // Batched launch: workgroup b runs workgroup map[b].block of grid map[b].item.
-template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
-__global__ __launch_bounds__(64 * NW) void sweep3d_batch_kernel(const Item3D<T, npts(3, R, BOX)>* __restrict__ items,
+template <typename T, int ACC, int EXPR, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
+__global__ __launch_bounds__(64 * NW) void sweep3d_batch_kernel(const Item3D<T, ncoef(3, R, BOX, EXPR)>* __restrict__ items,
                                                               const BlockMap* __restrict__ map) {
   __shared__ T xbuf[2][NW][2 * R][64 * CPL];
   const BlockMap m = map[xcd_logical_block(blockIdx.x, gridDim.x)];
-  const Item3D<T, npts(3, R, BOX)>& it = items[__builtin_amdgcn_readfirstlane(m.item)];
+  const Item3D<T, ncoef(3, R, BOX, EXPR)>& it = items[__builtin_amdgcn_readfirstlane(m.item)];
   const Sweep3DArgs a = it.a;
-  const CoefPack<T, npts(3, R, BOX)> cf = it.cf;
-  sweep3d_block<T, ACC, R, BOX, BT, CPL, M, NW, NR>(a, cf, __builtin_amdgcn_readfirstlane(m.block), xbuf);
+  const CoefPack<T, ncoef(3, R, BOX, EXPR)> cf = it.cf;
+  sweep3d_block<T, ACC, EXPR, R, BOX, BT, CPL, M, NW, NR>(a, cf, __builtin_amdgcn_readfirstlane(m.block), xbuf);
 }
 
 // Geometry of one grid's launch; returns its workgroup count (0 if it does
 // not fit a 32-bit grid).
-template <typename T, int R, bool BOX, int BT, int CPL, int M, int NW>
-int64_t make_args3d(const Round3D& rd, Sweep3DArgs& a, CoefPack<T, npts(3, R, BOX)>& cf) {
-  constexpr int NP = npts(3, R, BOX);
+template <typename T, int EXPR, int R, bool BOX, int BT, int CPL, int M, int NW>
+int64_t make_args3d(const Round3D& rd, Sweep3DArgs& a, CoefPack<T, ncoef(3, R, BOX, EXPR)>& cf) {
+  constexpr int NP = ncoef(3, R, BOX, EXPR);  // the divisor c0 last for EXPR_DIV
   constexpr int C1 = NW * M - 2 * BT * R, C2 = compute_width(64 * CPL, BT, R, sizeof(T));
   for (int k = 0; k < NP; ++k) cf.c[k] = static_cast<T>(rd.coeffs[k]);
   a.src = rd.src;
@@ -325,52 +325,52 @@ int64_t make_args3d(const Round3D& rd, Sweep3DArgs& a, CoefPack<T, npts(3, R, BO
   return nblk > INT32_MAX ? 0 : nblk;
 }
 
-template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
+template <typename T, int ACC, int EXPR, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
 hipError_t launch_sweep3d(const Round3D& rd) {
   Sweep3DArgs a;
-  CoefPack<T, npts(3, R, BOX)> cf;
-  const int64_t nblk = make_args3d<T, R, BOX, BT, CPL, M, NW>(rd, a, cf);
+  CoefPack<T, ncoef(3, R, BOX, EXPR)> cf;
+  const int64_t nblk = make_args3d<T, EXPR, R, BOX, BT, CPL, M, NW>(rd, a, cf);
   if (nblk == 0) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((sweep3d_kernel<T, ACC, R, BOX, BT, CPL, M, NW, NR>), dim3(static_cast<unsigned>(nblk)),
+  hipLaunchKernelGGL((sweep3d_kernel<T, ACC, EXPR, R, BOX, BT, CPL, M, NW, NR>), dim3(static_cast<unsigned>(nblk)),
                      dim3(64 * NW), 0, rd.stream, a, cf);
   return hipGetLastError();
 }
 
-template <typename T, int R, bool BOX, int BT, int CPL, int M, int NW>
+template <typename T, int EXPR, int R, bool BOX, int BT, int CPL, int M, int NW>
 int fill_item3d(void* item, const Round3D& rd) {
-  Item3D<T, npts(3, R, BOX)> it;
-  const int64_t nblk = make_args3d<T, R, BOX, BT, CPL, M, NW>(rd, it.a, it.cf);
+  Item3D<T, ncoef(3, R, BOX, EXPR)> it;
+  const int64_t nblk = make_args3d<T, EXPR, R, BOX, BT, CPL, M, NW>(rd, it.a, it.cf);
   __builtin_memcpy(item, &it, sizeof(it));
   return static_cast<int>(nblk);
 }
 
-template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
+template <typename T, int ACC, int EXPR, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
 hipError_t launch_batch3d(const void* items, const BlockMap* map, int nblocks, hipStream_t stream) {
-  hipLaunchKernelGGL((sweep3d_batch_kernel<T, ACC, R, BOX, BT, CPL, M, NW, NR>), dim3(nblocks), dim3(64 * NW), 0,
-                     stream, static_cast<const Item3D<T, npts(3, R, BOX)>*>(items), map);
+  hipLaunchKernelGGL((sweep3d_batch_kernel<T, ACC, EXPR, R, BOX, BT, CPL, M, NW, NR>), dim3(nblocks), dim3(64 * NW), 0,
+                     stream, static_cast<const Item3D<T, ncoef(3, R, BOX, EXPR)>*>(items), map);
   return hipGetLastError();
 }
 
-template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
+template <typename T, int ACC, int EXPR, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
 int occupancy_sweep3d() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep3d_kernel<T, ACC, R, BOX, BT, CPL, M, NW, NR>, 64 * NW,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep3d_kernel<T, ACC, EXPR, R, BOX, BT, CPL, M, NW, NR>, 64 * NW,
                                                    0) != hipSuccess)
     return 0;
   return nb;
 }
 
-template <typename T, int ACC, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
+template <typename T, int ACC, int EXPR, int R, bool BOX, int BT, int CPL, int M, int NW, int NR>
 Kernel3D make_kernel3d() {
-  return Kernel3D{&launch_sweep3d<T, ACC, R, BOX, BT, CPL, M, NW, NR>,
-                  &occupancy_sweep3d<T, ACC, R, BOX, BT, CPL, M, NW, NR>,
+  return Kernel3D{&launch_sweep3d<T, ACC, EXPR, R, BOX, BT, CPL, M, NW, NR>,
+                  &occupancy_sweep3d<T, ACC, EXPR, R, BOX, BT, CPL, M, NW, NR>,
                   CPL,
                   M,
                   NW,
                   BT,
-                  &fill_item3d<T, R, BOX, BT, CPL, M, NW>,
-                  &launch_batch3d<T, ACC, R, BOX, BT, CPL, M, NW, NR>,
-                  static_cast<int>(sizeof(Item3D<T, npts(3, R, BOX)>))};
+                  &fill_item3d<T, EXPR, R, BOX, BT, CPL, M, NW>,
+                  &launch_batch3d<T, ACC, EXPR, R, BOX, BT, CPL, M, NW, NR>,
+                  static_cast<int>(sizeof(Item3D<T, ncoef(3, R, BOX, EXPR)>))};
 }
 
 }  // namespace s5d

@@ -59,11 +59,22 @@ Rates device_rates() {
 double ops_per_cell(const s5d_plan* p, int cpl) {
   const int r = p->d.radius, nd = p->d.ndim;
   const bool box = p->d.shape == S5D_BOX;
-  const int n = static_cast<int>(p->coeffs.size());
+  const int n = static_cast<int>(p->expr == EXPR_LINEAR ? p->coeffs.size()
+                                                         : (box ? (nd == 2 ? (2 * r + 1) * (2 * r + 1)
+                                                                           : (2 * r + 1) * (2 * r + 1) * (2 * r + 1))
+                                                                : 2 * r * nd + 1));
   const int words = p->elem / 4;
   // terms: one FMA each, or the compensated sequence (two products split
   // exactly, a two-sum and two adds: nine operations) plus its final add
   double ops = p->kind == KIND_F32_COMP ? 9.0 * (n - 1) + 3.0 : static_cast<double>(n);
+  // expressions: an IEEE quotient (about 10 float32 / 16 float64 operations);
+  // gradient2d: 4 differences, 4 squares, 4 sums, a square root and a
+  // quotient (about 12 + 20 / 12 + 36) replacing the weighted sum; per-cell
+  // weights: one extra load per term (counted with the loads below)
+  const bool f64 = p->elem == 8;
+  if (p->expr == EXPR_DIV) ops = static_cast<double>(n - 1) + (f64 ? 16.0 : 10.0);
+  if (p->expr == EXPR_GRADIENT) ops = f64 ? 48.0 : 32.0;
+  if (p->expr == EXPR_VARCOEF) ops = static_cast<double>(n) * 1.5;
   // lane exchange: R cells from each neighbouring lane for every row that
   // needs in-row neighbours (one row for a star, 2r+1 rows or planes x rows
   // for a box), by 32-bit DPP moves -- except in the 2D plain float32 star
@@ -113,6 +124,12 @@ RoundModel model_round2d(const s5d_plan* p, int bt) {
       for (int T = 1; T <= bt; ++T) rows_comp += static_cast<double>(b - a) + 2.0 * (bt - T) * r;
     }
   m.gm = (rows_read * cols_read + static_cast<double>(I0) * cols_written) * w;
+  if (p->expr == EXPR_VARCOEF) {
+    // the weights of every cell, once per round from HBM (the levels re-read
+    // them from the caches)
+    const int n = p->d.shape == S5D_BOX ? (2 * r + 1) * (2 * r + 1) : 4 * r + 1;
+    m.gm += static_cast<double>(n) * static_cast<double>(I0) * static_cast<double>(I1) * w;
+  }
   m.ops = rows_comp * W * ntiles * ops_per_cell(p, cpl);
   m.wgs = (ntiles * blocks + kWavesPerBlock - 1) / kWavesPerBlock;
   const int occ = p->by_bt[bt].occupancy ? p->by_bt[bt].occupancy() : 0;
@@ -250,17 +267,21 @@ s5d_status model_plan(const s5d_plan* p, s5d_model* out) {
 // bucket of every extent.
 namespace {
 
-using Key = std::tuple<int, int, int, int, int, int, int, int>;
+using Key = std::tuple<int, int, int, int, int, int, int, int, int>;
 
 Key key_of(const s5d_desc& d) {
   auto bucket = [](int64_t x) { return x <= 1 ? 0 : static_cast<int>(std::ceil(std::log2(static_cast<double>(x)))); };
-  return Key{d.ndim, d.shape, d.radius, d.dtype, d.accum, bucket(d.interior[0]), bucket(d.interior[1]),
+  return Key{d.ndim, d.shape, d.radius, d.dtype, d.accum, d.expr, bucket(d.interior[0]), bucket(d.interior[1]),
              d.ndim == 3 ? bucket(d.interior[2]) : 0};
 }
 
+// The winner's stream-block length was measured for one set of extents: it is
+// kept for exactly those, while other extents of the same bucket have it
+// chosen again for their own size (stream_chunk = 0).
 struct CacheEntry {
   s5d_tuning tun;
   double sec_per_step;
+  int64_t interior[3];
 };
 
 std::mutex g_cache_mu;
@@ -273,6 +294,9 @@ bool tune_cache_lookup(const s5d_desc& d, s5d_tuning* tun) {
   auto it = g_cache.find(key_of(d));
   if (it == g_cache.end()) return false;
   *tun = it->second.tun;
+  bool same = true;
+  for (int a = 0; a < d.ndim; ++a) same = same && it->second.interior[a] == d.interior[a];
+  if (!same) tun->stream_chunk = 0;
   return true;
 }
 
@@ -290,8 +314,8 @@ struct Candidate {
 
 // Time one candidate: a sweep of two full rounds (2*b_T steps) on scratch
 // buffers, after one warm-up; returns seconds per time step.
-s5d_status measure(const s5d_desc& d, const s5d_tuning& tun, void* b0, void* b1, hipStream_t st, int reps,
-                   double* sec_per_step) {
+s5d_status measure(const s5d_desc& d, const s5d_tuning& tun, void* b0, void* b1, const void* fields, hipStream_t st,
+                   int reps, double* sec_per_step) {
   s5d_desc dd = d;
   dd.steps = 2LL * tun.bt;
   s5d_plan* p = nullptr;
@@ -300,9 +324,9 @@ s5d_status measure(const s5d_desc& d, const s5d_tuning& tun, void* b0, void* b1,
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  if (e == hipSuccess) rc = s5d_run(p, b0, b1, st, nullptr);
+  if (e == hipSuccess) rc = s5d_run_fields(p, b0, b1, fields, st, nullptr);
   if (e == hipSuccess && rc == S5D_OK) e = hipEventRecord(e0, st);
-  for (int i = 0; e == hipSuccess && rc == S5D_OK && i < reps; ++i) rc = s5d_run(p, b0, b1, st, nullptr);
+  for (int i = 0; e == hipSuccess && rc == S5D_OK && i < reps; ++i) rc = s5d_run_fields(p, b0, b1, fields, st, nullptr);
   if (e == hipSuccess && rc == S5D_OK) e = hipEventRecord(e1, st);
   if (e == hipSuccess && rc == S5D_OK) e = hipEventSynchronize(e1);
   float ms = 0;
@@ -367,12 +391,14 @@ s5d_status s5d_autotune(const s5d_desc* desc, int32_t top_k, void* stream, s5d_t
   if (desc->ndim == 2) {
     for (int i = 0; i < s5d::kRegistry2DSize; ++i) {
       const s5d::Entry2D& e = s5d::kRegistry2D[i];
-      if (e.dtype == kind && e.box == box && e.r == desc->radius) fams.emplace_back(e.cpl, 0, e.bt);
+      if (e.dtype == kind && e.expr == desc->expr && e.box == box && e.r == desc->radius)
+        fams.emplace_back(e.cpl, 0, e.bt);
     }
   } else {
     for (int i = 0; i < s5d::kRegistry3DSize; ++i) {
       const s5d::Entry3D& e = s5d::kRegistry3D[i];
-      if (e.dtype == kind && e.box == box && e.r == desc->radius) fams.emplace_back(e.cpl, e.m, e.bt);
+      if (e.dtype == kind && e.expr == desc->expr && e.box == box && e.r == desc->radius)
+        fams.emplace_back(e.cpl, e.m, e.bt);
     }
   }
   const int64_t I0 = desc->interior[0];
@@ -421,19 +447,30 @@ s5d_status s5d_autotune(const s5d_desc* desc, int32_t top_k, void* stream, s5d_t
   if (top_k > 0 && desc->steps > 0) {
     void* b0 = nullptr;
     void* b1 = nullptr;
+    void* fl = nullptr;
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = hipMalloc(&b0, static_cast<size_t>(bytes));
     if (e == hipSuccess) e = hipMalloc(&b1, static_cast<size_t>(bytes));
     if (e == hipSuccess) e = hipMemsetAsync(b0, 0, static_cast<size_t>(bytes), st);  // timing does not depend on values
+    if (e == hipSuccess && desc->expr == S5D_EXPR_VARCOEF) {
+      // per-cell weights for the timing runs (values do not matter either)
+      const int64_t np = box ? (desc->ndim == 2 ? 1LL : (2LL * desc->radius + 1)) * (2LL * desc->radius + 1) *
+                                   (2LL * desc->radius + 1)
+                             : 2LL * desc->radius * desc->ndim + 1;
+      const int64_t fb = np * desc->interior[0] * desc->interior[1] * (desc->dtype == S5D_F64 ? 8 : 4);
+      e = hipMalloc(&fl, static_cast<size_t>(fb));
+      if (e == hipSuccess) e = hipMemsetAsync(fl, 0, static_cast<size_t>(fb), st);
+    }
     if (e != hipSuccess) {
       if (b0) (void)hipFree(b0);
       if (b1) (void)hipFree(b1);
+      if (fl) (void)hipFree(fl);
       return device_fail(e, "autotune scratch buffers");
     }
     const int reps = 3;
     double best_t = 1e300;
     for (size_t i = 0; i < cands.size() && static_cast<int>(i) < top_k; ++i) {
-      rc = measure(*desc, cands[i].tun, b0, b1, st, reps, &cands[i].measured);
+      rc = measure(*desc, cands[i].tun, b0, b1, fl, st, reps, &cands[i].measured);
       if (rc != S5D_OK) break;
       ++n_measured;
       if (cands[i].measured < best_t) {
@@ -441,10 +478,11 @@ s5d_status s5d_autotune(const s5d_desc* desc, int32_t top_k, void* stream, s5d_t
         win = &cands[i];
       }
     }
-    if (rc == S5D_OK) rc = measure(*desc, base_tun, b0, b1, st, reps, &base_measured);
+    if (rc == S5D_OK) rc = measure(*desc, base_tun, b0, b1, fl, st, reps, &base_measured);
     (void)hipStreamSynchronize(st);
     (void)hipFree(b0);
     (void)hipFree(b1);
+    if (fl) (void)hipFree(fl);
     if (rc != S5D_OK) return rc;
     if (base_measured > 0 && base_measured < best_t) {
       // the library's own choice stays if no candidate beats it
@@ -455,7 +493,8 @@ s5d_status s5d_autotune(const s5d_desc* desc, int32_t top_k, void* stream, s5d_t
   *best = win->tun;
   {
     std::lock_guard<std::mutex> lk(s5d::g_cache_mu);
-    s5d::g_cache[s5d::key_of(*desc)] = s5d::CacheEntry{win->tun, win->measured};
+    s5d::g_cache[s5d::key_of(*desc)] =
+        s5d::CacheEntry{win->tun, win->measured, {desc->interior[0], desc->interior[1], desc->interior[2]}};
   }
   if (report) {
     report->n_candidates = static_cast<int32_t>(cands.size());
@@ -473,14 +512,18 @@ s5d_status s5d_tune_cache_save(const char* path) {
   FILE* f = std::fopen(path, "w");
   if (!f) return fail(S5D_EINVAL, std::string("cannot open ") + path);
   std::lock_guard<std::mutex> lk(s5d::g_cache_mu);
-  std::fprintf(f, "# stencil5d tuning cache v1: ndim shape radius dtype accum b0 b1 b2 : bt tile0 tile1 "
-                  "stream_chunk cells_per_lane rows_per_wave : seconds_per_step\n");
+  std::fprintf(f, "# stencil5d tuning cache v2: ndim shape radius dtype accum expr b0 b1 b2 : bt tile0 tile1 "
+                  "stream_chunk cells_per_lane rows_per_wave : seconds_per_step : interior0 interior1 "
+                  "interior2 (the extents stream_chunk was measured for)\n");
   for (const auto& kv : s5d::g_cache) {
     const auto& k = kv.first;
     const s5d_tuning& t = kv.second.tun;
-    std::fprintf(f, "%d %d %d %d %d %d %d %d : %d %d %d %d %d %d : %.9g\n", std::get<0>(k), std::get<1>(k),
-                 std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k), std::get<7>(k),
-                 t.bt, t.tile0, t.tile1, t.stream_chunk, t.cells_per_lane, t.rows_per_wave, kv.second.sec_per_step);
+    const int64_t* in = kv.second.interior;
+    std::fprintf(f, "%d %d %d %d %d %d %d %d %d : %d %d %d %d %d %d : %.9g : %lld %lld %lld\n", std::get<0>(k),
+                 std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k),
+                 std::get<7>(k), std::get<8>(k), t.bt, t.tile0, t.tile1, t.stream_chunk, t.cells_per_lane, t.rows_per_wave,
+                 kv.second.sec_per_step, static_cast<long long>(in[0]), static_cast<long long>(in[1]),
+                 static_cast<long long>(in[2]));
   }
   const bool ok = std::fclose(f) == 0;
   return ok ? S5D_OK : fail(S5D_EINVAL, std::string("write failed: ") + path);
@@ -496,10 +539,12 @@ s5d_status s5d_tune_cache_load(const char* path) {
   bool bad = false;
   while (std::fgets(line, sizeof(line), f)) {
     if (line[0] == '#' || line[0] == '\n') continue;
-    int k[8], t[6];
+    int k[9], t[6];
     double sec = 0;
-    if (std::sscanf(line, "%d %d %d %d %d %d %d %d : %d %d %d %d %d %d : %lf", &k[0], &k[1], &k[2], &k[3], &k[4],
-                    &k[5], &k[6], &k[7], &t[0], &t[1], &t[2], &t[3], &t[4], &t[5], &sec) != 15) {
+    long long in[3] = {0, 0, 0};
+    if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d : %d %d %d %d %d %d : %lf : %lld %lld %lld", &k[0], &k[1],
+                    &k[2], &k[3], &k[4], &k[5], &k[6], &k[7], &k[8], &t[0], &t[1], &t[2], &t[3], &t[4], &t[5], &sec,
+                    &in[0], &in[1], &in[2]) != 19) {
       bad = true;
       break;
     }
@@ -512,7 +557,8 @@ s5d_status s5d_tune_cache_load(const char* path) {
     tun.stream_chunk = t[3];
     tun.cells_per_lane = t[4];
     tun.rows_per_wave = t[5];
-    loaded[s5d::Key{k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7]}] = s5d::CacheEntry{tun, sec};
+    loaded[s5d::Key{k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7], k[8]}] =
+        s5d::CacheEntry{tun, sec, {static_cast<int64_t>(in[0]), static_cast<int64_t>(in[1]), static_cast<int64_t>(in[2])}};
   }
   std::fclose(f);
   if (bad) return fail(S5D_EINVAL, std::string("malformed tuning cache: ") + path);

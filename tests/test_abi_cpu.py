@@ -197,3 +197,68 @@ def test_direct_plan_needs_a_device():
         _lib.load().s5d_plan_destroy(h)
     else:
         assert st == _lib.S5D_EDEVICE, _lib.last_error()
+
+
+def _create_expr(expr, ndim=2, radius=1, box=False, dtype=_lib.F64, accum=0, interior=(64, 64),
+                 steps=4, coeffs=None, tuning=None):
+    lib = _lib.load()
+    d, keep = _lib.make_desc(ndim, radius, box, dtype, accum, interior, steps, coeffs, expr)
+    h = ctypes.c_void_p()
+    st = lib.s5d_plan_create(ctypes.byref(d), ctypes.byref(tuning) if tuning else None, ctypes.byref(h))
+    if st == _lib.S5D_OK:
+        lib.s5d_plan_destroy(h)
+    return st
+
+
+def test_expression_descriptor_validation():
+    """Coefficient counts per expression, the gradient2d shape, the divisor,
+    compensated accumulation and direct kernels (all checked on the host)."""
+    E = _lib
+    ok = E.S5D_OK
+    assert _create_expr(E.EXPR_DIV, coeffs=[1, 2, 3, 4, 5, 15]) == ok            # j2d5pt
+    assert _create_expr(E.EXPR_DIV, coeffs=[1, 2, 3, 4, 5]) == E.S5D_EINVAL      # c0 missing
+    assert _create_expr(E.EXPR_DIV, coeffs=[1, 2, 3, 4, 5, 0]) == E.S5D_EINVAL   # c0 = 0
+    assert _create_expr(E.EXPR_DIV, radius=2, coeffs=np.ones(10)) == ok          # j2d9pt
+    assert _create_expr(E.EXPR_DIV, box=True, coeffs=np.ones(10)) == ok          # j2d9pt-gol
+    assert _create_expr(E.EXPR_DIV, ndim=3, box=True, interior=(20, 30, 40), coeffs=np.ones(28)) == ok
+    assert _create_expr(E.EXPR_GRADIENT, coeffs=[0.5, 1.5]) == ok
+    assert _create_expr(E.EXPR_GRADIENT, coeffs=[0.5]) == E.S5D_EINVAL
+    assert _create_expr(E.EXPR_GRADIENT, radius=2, coeffs=[0.5, 1.5]) == E.S5D_EINVAL
+    assert _create_expr(E.EXPR_GRADIENT, box=True, coeffs=[0.5, 1.5]) == E.S5D_EINVAL
+    assert _create_expr(E.EXPR_GRADIENT, ndim=3, interior=(8, 8, 8), coeffs=[0.5, 1.5]) == E.S5D_EINVAL
+    assert _create_expr(E.EXPR_VARCOEF, coeffs=None) == ok
+    assert _create_expr(E.EXPR_VARCOEF, coeffs=[0.2] * 5) == E.S5D_EINVAL
+    assert _create_expr(E.EXPR_VARCOEF, ndim=3, interior=(8, 8, 8)) == E.S5D_EUNSUPPORTED
+    assert _create_expr(E.EXPR_DIV, radius=4, coeffs=np.ones(18)) == E.S5D_EUNSUPPORTED
+    assert _create_expr(E.EXPR_DIV, dtype=E.F32, accum=E.ACC_COMPENSATED,
+                        coeffs=[1, 2, 3, 4, 5, 15]) == E.S5D_EUNSUPPORTED
+    assert _create_expr(E.EXPR_DIV, coeffs=[1, 2, 3, 4, 5, 15],
+                        tuning=_lib.make_tuning(kernel=2)) == E.S5D_EUNSUPPORTED
+    assert _create_expr(7, coeffs=[1.0] * 5) == E.S5D_EINVAL
+
+
+def test_run_fields_validation():
+    lib = _lib.load()
+    d, keep = _lib.make_desc(2, 1, False, _lib.F64, 0, (64, 64), 4, None, _lib.EXPR_VARCOEF)
+    h = ctypes.c_void_p()
+    assert lib.s5d_plan_create(ctypes.byref(d), None, ctypes.byref(h)) == _lib.S5D_OK
+    idx = ctypes.c_int32()
+    vp = ctypes.c_void_p
+    # s5d_run refuses a plan with per-cell weights; s5d_run_fields needs them
+    assert lib.s5d_run(h, vp(1 << 20), vp(1 << 28), None, ctypes.byref(idx)) == _lib.S5D_EINVAL
+    assert lib.s5d_run_fields(h, vp(1 << 20), vp(1 << 28), None, None, ctypes.byref(idx)) == _lib.S5D_EINVAL
+    assert lib.s5d_run_fields(h, vp(1 << 20), vp(1 << 28), vp((1 << 30) + 4), None,
+                              ctypes.byref(idx)) == _lib.S5D_EINVAL  # misaligned
+    lib.s5d_plan_destroy(h)
+    st, h = _create(steps=0)
+    assert st == _lib.S5D_OK
+    # fields given for a plan without per-cell weights
+    assert lib.s5d_run_fields(h, vp(1 << 20), vp(1 << 28), vp(1 << 30), None,
+                              ctypes.byref(idx)) == _lib.S5D_EINVAL
+    assert lib.s5d_run_fields(h, vp(1 << 20), vp(1 << 28), None, None, ctypes.byref(idx)) == _lib.S5D_OK
+    lib.s5d_plan_destroy(h)
+
+
+def test_waves_per_eu_is_reserved():
+    st, _ = _create(tuning=_lib.make_tuning(waves_per_eu=2))
+    assert st == _lib.S5D_EINVAL

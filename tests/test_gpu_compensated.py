@@ -17,8 +17,8 @@ from paper_2001_01473_amd import build as s5d_build
 
 pytestmark = pytest.mark.gpu
 
-V2 = [v for v in s5d_build.variants_2d() if v[0] == 2]
-V3 = [v for v in s5d_build.variants_3d() if v[0] == 2]
+V2 = [v for v in s5d_build.linear_variants_2d() if v[0] == 2]
+V3 = [v for v in s5d_build.linear_variants_3d() if v[0] == 2]
 
 
 def _signed_case(seed, ndim, r, box, interior, steps):

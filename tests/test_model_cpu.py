@@ -108,8 +108,18 @@ def test_autotune_model_only_and_cache_roundtrip(tmp_path):
               coeffs=np.full(5, 0.2))
     tun, rep = s5d.autotune(top_k=0, **kw)
     assert rep["n_candidates"] > 20 and rep["n_measured"] == 0
-    # a later plan without tuning, same stencil and extent bucket, takes the cached choice
+    # a later plan without tuning, same stencil and extent bucket, takes the
+    # cached depth and tile; the stream-block length is the cached one for the
+    # very extents it was chosen for, and chosen again for other extents
     p = s5d.Plan(**{**kw, "interior": (2900, 1900)})
+    got = p.query()
+    assert (got["bt"], got["cells_per_lane"]) == (tun["bt"], tun["cells_per_lane"])
+    own = s5d.Plan(**{**kw, "interior": (2900, 1900)}, bt=tun["bt"],
+                   cells_per_lane=tun["cells_per_lane"])
+    assert got["stream_chunk"] == own.query()["stream_chunk"]
+    own.close()
+    p.close()
+    p = s5d.Plan(**kw)
     got = p.query()
     assert (got["bt"], got["cells_per_lane"], got["stream_chunk"]) == \
         (tun["bt"], tun["cells_per_lane"], tun["stream_chunk"])
