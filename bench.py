@@ -781,6 +781,92 @@ def accuracy_full(which="all", md=None, n2=N, n3=N3, stencils2d=STENCILS):
     return rows
 
 
+def model_accuracy(md=None, kinds=(0, 1), top=5):
+    """Performance model against measurement (AN5D "Model Accuracy"): every
+    compiled blocked variant of the six 2D stencils at 16384^2 and of the
+    7-point star and 27-point box at 512^3, T = 1000, library-chosen stream
+    blocks.  For each stencil: the model's predicted and the measured time of
+    every variant, whether the model's top `top` holds the measured best, and
+    Tuned / Model = (model-predicted time of the model's best) / (measured
+    time of the best of the model's top `top`)."""
+    import torch
+    import paper_2001_01473_amd as s5d
+    from paper_2001_01473_amd import build as lib_build
+    groups = {}
+    for kind, box, r, cpl, bt, nr in lib_build.linear_variants_2d():
+        if kind in kinds and (r, bool(box)) in STENCILS:
+            groups.setdefault((2, kind, r, bool(box)), []).append(dict(bt=bt, cells_per_lane=cpl))
+    for kind, box, r, cpl, m, nw, bt, nr in lib_build.linear_variants_3d():
+        if kind in kinds and r == 1:
+            groups.setdefault((3, kind, r, bool(box)), []).append(
+                dict(bt=bt, cells_per_lane=cpl, rows_per_wave=m, tile0=m * nw))
+    summary, rows = [], []
+    for (nd, kind, r, box), tunings in sorted(groups.items()):
+        dtype, accum = KINDS[kind]
+        interior = (N, N) if nd == 2 else (N3, N3, N3)
+        name = "%s%dd%dr" % ("box" if box else "star", nd, r)
+        base = Problem(r, box, dtype, interior=interior, accum=accum)
+        cand = []
+        for tun in tunings:
+            try:
+                plan = s5d.Plan(ndim=nd, radius=r, box=box, dtype=dtype, interior=interior, steps=T_STEPS,
+                                coeffs=base.coeffs, accum=accum, **tun)
+            except Exception as e:  # noqa: BLE001 - reported, not fatal
+                print(json.dumps({"stencil": name, "kind": KIND_NAMES[kind], "tuning": tun,
+                                  "error": str(e)[:120]}), flush=True)
+                continue
+            base.plan.close()
+            base.plan, base.info = plan, plan.query()
+            pred = plan.model()["seconds"]
+            meas = time_steps(base, 1, 1)
+            row = {"stencil": name, "kind": KIND_NAMES[kind], "bt": base.info["bt"],
+                   "tile": [base.info["tile0"], base.info["tile1"]] if nd == 3 else [base.info["tile0"]],
+                   "stream_chunk": base.info["stream_chunk"], "model_s": pred, "measured_s": meas,
+                   "measured_over_model": meas / pred}
+            rows.append(row)
+            cand.append(row)
+            print(json.dumps(row), flush=True)
+        base.close()
+        torch.cuda.empty_cache()
+        if not cand:
+            continue
+        by_model = sorted(cand, key=lambda x: x["model_s"])
+        best = min(cand, key=lambda x: x["measured_s"])
+        tuned = min(by_model[:top], key=lambda x: x["measured_s"])
+        cells = float(np.prod(interior)) * T_STEPS
+        summary.append({"stencil": name, "kind": KIND_NAMES[kind], "variants": len(cand),
+                        "model_best_bt": by_model[0]["bt"], "model_best_gcells": cells / by_model[0]["model_s"] / 1e9,
+                        "tuned_bt": tuned["bt"], "tuned_gcells": cells / tuned["measured_s"] / 1e9,
+                        "measured_best_bt": best["bt"], "measured_best_gcells": cells / best["measured_s"] / 1e9,
+                        "best_in_top": best in by_model[:top],
+                        "tuned_over_model": by_model[0]["model_s"] / tuned["measured_s"]})
+        print(json.dumps(summary[-1]), flush=True)
+    if md:
+        with open(md, "w") as f:
+            f.write("# Performance model against measurement\n\n")
+            f.write("Command (from the repository root): `python bench.py --model-accuracy --md <this file>`\n\n")
+            f.write("Every compiled blocked variant of each stencil (2D at 16384^2, 3D at 512^3, T = 1000, "
+                    "stream blocks chosen by the library), predicted by `s5d_plan_model` and timed once after "
+                    "one warm-up sweep (HIP events).  *Tuned* is the best measured of the model's top %d; "
+                    "Tuned / Model is the model's predicted rate for its best over Tuned's measured rate "
+                    "(AN5D \"Model Accuracy\").\n\n" % top)
+            f.write("| stencil | kind | variants | model best b_T | model GCell/s | tuned b_T | tuned GCell/s | "
+                    "measured best b_T | measured best GCell/s | best in model top %d | Tuned / Model |\n"
+                    "|---|---|---|---|---|---|---|---|---|---|---|\n" % top)
+            for x in summary:
+                f.write("| %s | %s | %d | %d | %.0f | %d | %.0f | %d | %.0f | %s | %.2f |\n" % (
+                    x["stencil"], x["kind"], x["variants"], x["model_best_bt"], x["model_best_gcells"],
+                    x["tuned_bt"], x["tuned_gcells"], x["measured_best_bt"], x["measured_best_gcells"],
+                    "yes" if x["best_in_top"] else "no", x["tuned_over_model"]))
+            f.write("\n## Every variant\n\n| stencil | kind | b_T | tile | h_SN | model ms | measured ms | "
+                    "measured / model |\n|---|---|---|---|---|---|---|---|\n")
+            for x in rows:
+                f.write("| %s | %s | %d | %s | %d | %.2f | %.2f | %.2f |\n" % (
+                    x["stencil"], x["kind"], x["bt"], "x".join(str(t) for t in x["tile"]), x["stream_chunk"],
+                    x["model_s"] * 1e3, x["measured_s"] * 1e3, x["measured_over_model"]))
+    return summary
+
+
 def summarize_pmc(d, kernel):
     """Markdown table of per-dispatch counter averages (rocprofv3 --pmc CSV)."""
     import csv
@@ -910,6 +996,9 @@ def main(argv=None):
     ap.add_argument("--accuracy-full", nargs="?", const="all", choices=("all", "2d", "3d"),
                     help="compare whole T = 1000 grids at the benchmark sizes with the CPU oracle")
     ap.add_argument("--expr", action="store_true", help="time only the expression stencils")
+    ap.add_argument("--model-accuracy", action="store_true",
+                    help="predicted against measured time of every blocked variant (with --md: a table)")
+    ap.add_argument("--model-kinds", default="0,1", help="with --model-accuracy: kinds (0 f32, 1 f64, 2 f32c)")
     ap.add_argument("--md", default=None, help="with --accuracy-full: write a markdown table here")
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-loads", default="0.5,0.9")
@@ -955,6 +1044,9 @@ def main(argv=None):
     if args.accuracy_full:
         rows = accuracy_full(args.accuracy_full, args.md)
         return 0 if all(r["ok"] for r in rows) else 1
+    if args.model_accuracy:
+        model_accuracy(args.md, kinds=tuple(int(k) for k in args.model_kinds.split(",")))
+        return 0
 
     extras = {}
     if args.accuracy:

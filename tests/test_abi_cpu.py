@@ -72,7 +72,7 @@ FULL = dict(bt=2, stream_chunk=32, cells_per_lane=4)
     (dict(dtype=7), _lib.S5D_EINVAL),
     (dict(accum=1, dtype=_lib.F64), _lib.S5D_EINVAL),
     (dict(coeffs=np.array([0.2, 0.2, np.nan, 0.2, 0.2])), _lib.S5D_EINVAL),
-    (dict(radius=3, box=True), _lib.S5D_EUNSUPPORTED),
+    (dict(radius=4, box=True), _lib.S5D_EUNSUPPORTED),  # float64 81-point box: no b_T = 2 variant fits
     (dict(radius=5), _lib.S5D_EUNSUPPORTED),
 ])
 def test_plan_create_rejects(kw, code):
@@ -185,7 +185,7 @@ def test_kernel_family_validation():
     st, _ = _create(tuning=_lib.make_tuning(kernel="direct", bt=2))
     assert st == _lib.S5D_EINVAL
     # blocking asked for a stencil without a blocked variant
-    st, _ = _create(radius=3, box=True, tuning=_lib.make_tuning(kernel="blocked"))
+    st, _ = _create(ndim=3, radius=3, interior=(8, 8, 8), tuning=_lib.make_tuning(kernel="blocked"))
     assert st == _lib.S5D_EUNSUPPORTED
 
 
