@@ -431,6 +431,26 @@ s5d_status s5d_error_norms(const void *got, int32_t got_dtype, const void *ref, 
                            int64_t n, double *out, void *workspace, int64_t workspace_bytes,
                            void *stream);
 
+/* s5d_error_norms without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same inputs, outputs, results (bit for
+ * bit) and errors as s5d_error_norms, except:
+ *   - the first-pass partials go to a fixed scratch array in device memory
+ *     that the library holds for each GPU until the process ends
+ *     (2048 x 5 doubles = 80 KiB; the first pass never uses more than 2048
+ *     workgroups, so every n >= 0 fits; a larger need would be rejected
+ *     with S5D_EINVAL);
+ *   - the scratch of the current device is used, and a non-NULL `stream`
+ *     must belong to that device (S5D_EINVAL otherwise);
+ *   - no call allocates or frees memory; the scratch keeps the last call's
+ *     partials, and every value the final pass reads is written by the same
+ *     call first, so nothing needs clearing.
+ * Calls that overlap on one GPU (on different streams, or from several
+ * threads without ordering) share that scratch and race: order them on one
+ * stream, or use s5d_error_norms with a workspace of their own. */
+s5d_status s5d_error_norms_noalloc(const void *got, int32_t got_dtype, const void *ref, int32_t ref_dtype,
+                                   int64_t n, double *out, void *stream);
+
 /* Human-readable name of a status code (static storage). */
 const char *s5d_status_string(s5d_status status);
 

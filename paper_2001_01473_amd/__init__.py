@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import (ACC_COMPENSATED, ACC_PLAIN, BOX, EXPR_DIV, EXPR_GRADIENT, EXPR_LINEAR,
                    EXPR_VARCOEF, F32, F64, STAR, Stencil5DError, last_error, status_string)
 
-__all__ = ["Plan", "Batch", "Server", "solve", "error_norms", "autotune", "tune_cache_save",
+__all__ = ["Plan", "Batch", "Server", "solve", "error_norms", "error_norms_noalloc", "autotune", "tune_cache_save",
            "tune_cache_load", "tune_cache_clear", "NORM_NAMES", "Stencil5DError", "status_string",
            "last_error",
            "STAR", "BOX", "F32", "F64", "ACC_PLAIN", "ACC_COMPENSATED",
@@ -418,4 +418,30 @@ def error_norms(got, ref, *, stream=None, out=None, workspace=None):
                                    ctypes.c_void_p(workspace.data_ptr()),
                                    int(workspace.numel() * workspace.element_size()),
                                    ctypes.c_void_p(handle)), "s5d_error_norms")
+    return out
+
+
+def error_norms_noalloc(got, ref, out, *, stream=None):
+    """``error_norms`` through ``s5d_error_norms_noalloc``: the partials go to
+    the library's fixed per-device scratch, so neither this call nor the
+    library allocates.  ``out`` (a float64 device tensor of NORMS_COUNT
+    values on the current device) receives the result and is returned.  Calls
+    that overlap on one GPU race on that scratch."""
+    import torch
+    lib = _lib.load()
+    for t in (got, ref, out):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("got, ref and out must be contiguous device tensors")
+    n = got.numel()
+    if ref.numel() != n:
+        raise ValueError("got and ref differ in size")
+    if out.dtype != torch.float64 or out.numel() < _lib.NORMS_COUNT:
+        raise ValueError("out must be a float64 tensor of %d values" % _lib.NORMS_COUNT)
+    if stream is None:
+        stream = torch.cuda.current_stream(got.device)
+    handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    _lib.check(lib.s5d_error_norms_noalloc(ctypes.c_void_p(got.data_ptr()), _dtype_code(got.dtype),
+                                           ctypes.c_void_p(ref.data_ptr()), _dtype_code(ref.dtype),
+                                           int(n), ctypes.c_void_p(out.data_ptr()),
+                                           ctypes.c_void_p(handle)), "s5d_error_norms_noalloc")
     return out

@@ -32,7 +32,7 @@ EXPORTS = ("s5d_plan_create", "s5d_plan_destroy", "s5d_plan_query", "s5d_run", "
            "s5d_server_get_stats",
            "s5d_plan_model", "s5d_autotune", "s5d_tune_cache_save", "s5d_tune_cache_load",
            "s5d_tune_cache_clear",
-           "s5d_error_norms_workspace_bytes", "s5d_error_norms",
+           "s5d_error_norms_workspace_bytes", "s5d_error_norms", "s5d_error_norms_noalloc",
            "s5d_status_string", "s5d_last_error")
 NORMS_COUNT = 5
 BATCH_GRAPH = 1
@@ -190,6 +190,9 @@ def load():
         lib.s5d_error_norms.restype = ctypes.c_int32
         lib.s5d_error_norms.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_int64,
                                         vp, vp, ctypes.c_int64, vp]
+        lib.s5d_error_norms_noalloc.restype = ctypes.c_int32
+        lib.s5d_error_norms_noalloc.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_int64,
+                                                vp, vp]
         lib.s5d_status_string.restype = ctypes.c_char_p
         lib.s5d_status_string.argtypes = [ctypes.c_int32]
         lib.s5d_last_error.restype = ctypes.c_char_p

@@ -754,4 +754,37 @@ s5d_status s5d_error_norms(const void* got, int32_t got_dtype, const void* ref, 
   return S5D_OK;
 }
 
+s5d_status s5d_error_norms_noalloc(const void* got, int32_t got_dtype, const void* ref, int32_t ref_dtype,
+                                   int64_t n, double* out, void* stream) {
+  g_last_error.clear();
+  if (n < 0) return fail(S5D_EINVAL, "n must be >= 0");
+  if ((got_dtype != S5D_F32 && got_dtype != S5D_F64) || (ref_dtype != S5D_F32 && ref_dtype != S5D_F64))
+    return fail(S5D_EINVAL, "dtypes must be S5D_F32 or S5D_F64");
+  if (!out) return fail(S5D_EINVAL, "out must not be NULL");
+  if (n > 0 && (!got || !ref)) return fail(S5D_EINVAL, "got and ref must not be NULL");
+  if ((n > 0 && ((reinterpret_cast<uintptr_t>(got) | reinterpret_cast<uintptr_t>(ref)) & 15)) ||
+      (reinterpret_cast<uintptr_t>(out) & 7))
+    return fail(S5D_EINVAL, "got and ref must be 16-byte aligned, out 8-byte aligned");
+  const int64_t need = s5d_error_norms_workspace_bytes(n);
+  if (need > s5d::error_norms_scratch_bytes())
+    return fail(S5D_EINVAL, "n needs " + std::to_string(need) + " bytes of partials, more than the " +
+                                std::to_string(s5d::error_norms_scratch_bytes()) + "-byte scratch");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+  if (stream) {
+    hipDevice_t sdev = -1;
+    e = hipStreamGetDevice(static_cast<hipStream_t>(stream), &sdev);
+    if (e != hipSuccess) return device_fail(e, "hipStreamGetDevice");
+    if (sdev != dev) return fail(S5D_EINVAL, "stream belongs to another device than the current one");
+  }
+  double* scratch = nullptr;
+  e = s5d::error_norms_scratch(&scratch);
+  if (e != hipSuccess) return device_fail(e, "address of the norm scratch");
+  e = s5d::launch_error_norms(got, got_dtype == S5D_F64, ref, ref_dtype == S5D_F64, n, out, scratch,
+                              s5d::error_norms_parts(n), static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "error-norm launch");
+  return S5D_OK;
+}
+
 }  // extern "C"

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "norms.h"
 
 namespace s5d {
@@ -172,6 +174,36 @@ hipError_t launch_norms_typed(const void* g, const void* o, int64_t n, double* o
 }
 
 }  // namespace
+
+// Scratch of the allocation-free entry point: room for the first-pass partials
+// of one call at the largest launch (kNormMaxParts workgroups x five values,
+// 80 KiB).  Each device holds its own copy for the life of the process.  In
+// host code this name is only a stand-in for the symbol, never a device
+// address: kernels get the address that hipGetSymbolAddress returns.
+static __device__ __align__(256) double scratch[kNormMaxParts * kNormVals];
+
+hipError_t error_norms_scratch(double** out) {
+  // one resolved address per device, looked up with that device current
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = static_cast<double*>(p);
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
+
+int64_t error_norms_scratch_bytes() { return static_cast<int64_t>(sizeof(scratch)); }
 
 int error_norms_parts(int64_t n) {
   // at least four 4-element vectors per thread, and at most kNormMaxParts
