@@ -297,16 +297,20 @@ def bench_plain512(reps=20):
 N3 = 512
 
 
-def full_sweep3d():
-    """Every compiled 3D variant at 512^3, T = 1000 (one warm-up, one timed run)."""
+def full_sweep3d(only=None, direct=True):
+    """Every compiled 3D variant at 512^3, T = 1000 (one warm-up, one timed run);
+    `only`: a regular expression on "<stencil> <kind>" (e.g. "star3d1r f32$")."""
+    import re
     import torch
     from paper_2001_01473_amd import build as lib_build
     for kind, box, r, cpl, m, nw, bt, nr in lib_build.linear_variants_3d():
         dtype, accum = KINDS[kind]
         name = "%s3d%dr" % ("box" if box else "star", r)
+        if only and not re.search(only, "%s %s" % (name, KIND_NAMES[kind])):
+            continue
         try:
             p = Problem(r, bool(box), dtype, interior=(N3, N3, N3), bt=bt, cells_per_lane=cpl,
-                        rows_per_wave=m, accum=accum)
+                        rows_per_wave=m, tile0=m * nw, accum=accum)
         except Exception as e:  # noqa: BLE001 - reported, not fatal
             print(json.dumps({"stencil": name, "kind": KIND_NAMES[kind], "bt": bt,
                               "tile": [nw * m, 64 * cpl], "error": str(e)[:120]}), flush=True)
@@ -319,7 +323,7 @@ def full_sweep3d():
         p.close()
         torch.cuda.empty_cache()
     # the direct kernels (one step per launch) for every 3D stencil and kind
-    for kind in (0, 1, 2):
+    for kind in ((0, 1, 2) if direct else ()):
         dtype, accum = KINDS[kind]
         for r in (1, 2, 3, 4):
             for box in (False, True):
@@ -530,6 +534,12 @@ def bench_batch(reps=2):
                 res["batched_graph" if graph else "batched_eager"] = _timed(batch.run, reset, reps)
                 out["launches_batched"] = batch.query()["launches"]
                 batch.close()
+            for graph in (False, True):
+                batch = s5d.Batch(plans, b0, b1, graph=graph, persistent=True)
+                res["persistent_graph" if graph else "persistent_eager"] = _timed(batch.run, reset, reps)
+                batch.status()
+                out["launches_persistent"] = batch.query()["launches"]
+                batch.close()
             out["launches_sequential"] = sum(
                 1 + -(-p.steps // p.query()["bt"]) for p in plans)
         for k, sec in res.items():
@@ -542,6 +552,9 @@ def bench_batch(reps=2):
         torch.cuda.empty_cache()
     out["speedup_vs_sequential_f32"] = (out["batched_graph_f32_gcells"] /
                                         out["sequential_f32_gcells"])
+    out["persistent_speedup_vs_sequential_f32"] = (out["persistent_graph_f32_gcells"] /
+                                                   out["sequential_f32_gcells"])
+    out["persistent_vs_plain_f64"] = out["persistent_graph_f32_gcells"] / out["sequential_sync_f64_gcells"]
     return out
 
 
@@ -988,6 +1001,7 @@ def main(argv=None):
                     help="time every compiled (stencil, dtype, b_T, cells per lane) at the "
                          "benchmark size and print one JSON line per variant")
     ap.add_argument("--launches", type=int, default=3)
+    ap.add_argument("--only", default=None, help="with --full-sweep3d: regex on '<stencil> <kind>'")
     ap.add_argument("--batch", action="store_true",
                     help="also measure the 64-grid batched workload")
     ap.add_argument("--serve", action="store_true", help="also measure the serving loop")
@@ -1036,7 +1050,7 @@ def main(argv=None):
         full_sweep()
         return 0
     if args.full_sweep3d:
-        full_sweep3d()
+        full_sweep3d(args.only, direct=not args.only)
         return 0
     if args.expr:
         print(json.dumps(sweep_expr()))

@@ -56,6 +56,7 @@ typedef int32_t s5d_status;
 #define S5D_EDEVICE 4      /* a HIP runtime call failed; see s5d_last_error() */
 #define S5D_EBUDGET 5      /* a memory budget would be exceeded */
 #define S5D_ECANCELED 6    /* a served request was cancelled (s5d_server_cancel) */
+#define S5D_ETIMEDOUT 7    /* a persistent batch's bounded wait ran out (s5d_batch_status) */
 
 /* Stencil shape (Background "Stencil Computation"). */
 #define S5D_STAR 0
@@ -254,6 +255,23 @@ typedef struct s5d_batch s5d_batch; /* opaque */
 
 #define S5D_BATCH_GRAPH 1 /* flag: capture the whole sequence into a HIP graph on the
                              first run and replay it with one graph launch */
+#define S5D_BATCH_PERSISTENT 2 /* flag: one persistent launch per stencil family
+                             (element type, accumulation, shape, radius, cells
+                             per lane) runs every round of that family's grids.
+                             Its workgroups (at most as many as are resident at
+                             once) take (grid, round, workgroup) items from a
+                             device queue ordered by round index; a grid's round
+                             k starts once every workgroup of its round k-1 has
+                             finished, with no device-wide barrier between round
+                             indices.  Results are bit for bit those of s5d_run.
+                             2D blocked plans of the families the library
+                             builds (plain float32 stars r <= 2 and 9-point
+                             boxes, plain float64 stars r <= 2, default cells per
+                             lane; b_T up to the family's deepest); any other
+                             plan gives S5D_EUNSUPPORTED at creation.  A waiting
+                             workgroup polls at most a bounded number of times
+                             (s5d_batch_set_wait_limit); s5d_batch_status reports
+                             a wait that ran out. */
 
 /* Build a batch over n grids.  plans[i] (not retained: it may be destroyed
  * afterwards; the batch keeps a reference to whatever device state of the
@@ -277,6 +295,27 @@ s5d_status s5d_batch_run(s5d_batch *batch, void *stream, int32_t *result_index);
 /* Launches per run (the one boundary-copy launch that covers every grid
  * included) and the number of round indices (may be NULL). */
 s5d_status s5d_batch_query(const s5d_batch *batch, int32_t *n_launches, int32_t *n_round_steps);
+
+/* Persistent batches: the number of persistent launches (stencil families),
+ * and their workgroups and work items summed over the launches (each may be
+ * NULL; all 0 for other batches).  Errors: S5D_EINVAL (NULL batch). */
+s5d_status s5d_batch_persistent_info(const s5d_batch *batch, int32_t *n_launches, int64_t *workgroups,
+                                     int64_t *items);
+
+/* Persistent batches (S5D_BATCH_PERSISTENT): synchronise `stream` (the
+ * stream of the last run), then read the launches' status.  S5D_OK if every
+ * dependency wait of the last run was satisfied, S5D_ETIMEDOUT if a wait ran
+ * out of polls (the run stopped early and its results are incomplete; the
+ * batch may be run again), S5D_EDEVICE if the synchronisation failed.  For
+ * other batches, S5D_OK after the synchronisation. */
+s5d_status s5d_batch_status(s5d_batch *batch, void *stream);
+
+/* Persistent batches: the most polls (each about a microsecond) a workgroup
+ * spends waiting for its grid's previous round before it gives up and the run
+ * stops with S5D_ETIMEDOUT.  polls >= 0; the default, 2^24, is seconds, far
+ * above any legitimate wait.  Takes effect at the next run (a captured graph
+ * is captured again).  Errors: S5D_EINVAL (NULL batch, polls < 0). */
+s5d_status s5d_batch_set_wait_limit(s5d_batch *batch, int64_t polls);
 
 /* Wait for the device to drain, then release the batch (NULL accepted). */
 void s5d_batch_destroy(s5d_batch *batch);

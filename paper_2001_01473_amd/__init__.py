@@ -177,11 +177,13 @@ def _check_pair(plan, b0, b1):
 
 class Batch:
     """Many independent sweeps run together (``s5d_batch``): per round index,
-    one launch per kernel variant over all grids; optionally replayed as one
-    HIP graph.  ``plans``, ``bufs0`` and ``bufs1`` are equal-length lists; the
-    buffers are bound to the batch and must outlive it."""
+    one launch per kernel variant over all grids, or (``persistent=True``) one
+    persistent launch per stencil family over every round of its grids;
+    optionally replayed as one HIP graph.  ``plans``, ``bufs0`` and ``bufs1``
+    are equal-length lists; the buffers are bound to the batch and must outlive
+    it."""
 
-    def __init__(self, plans, bufs0, bufs1, *, graph=False):
+    def __init__(self, plans, bufs0, bufs1, *, graph=False, persistent=False):
         lib = _lib.load()
         n = len(plans)
         if not (len(bufs0) == len(bufs1) == n):
@@ -198,8 +200,8 @@ class Batch:
         b0 = arr(*[vp(b.data_ptr()) for b in bufs0])
         b1 = arr(*[vp(b.data_ptr()) for b in bufs1])
         h = vp()
-        _lib.check(lib.s5d_batch_create(hp, b0, b1, n, _lib.BATCH_GRAPH if graph else 0,
-                                        ctypes.byref(h)), "s5d_batch_create")
+        flags = (_lib.BATCH_GRAPH if graph else 0) | (_lib.BATCH_PERSISTENT if persistent else 0)
+        _lib.check(lib.s5d_batch_create(hp, b0, b1, n, flags, ctypes.byref(h)), "s5d_batch_create")
         self._h = h
 
     def run(self, stream=None):
@@ -212,10 +214,27 @@ class Batch:
         return [int(idx[i]) for i in range(self.n)]
 
     def query(self) -> dict:
+        lib = _lib.load()
         nl, ns = ctypes.c_int32(), ctypes.c_int32()
-        _lib.check(_lib.load().s5d_batch_query(self._h, ctypes.byref(nl), ctypes.byref(ns)),
-                   "s5d_batch_query")
-        return {"launches": int(nl.value), "round_steps": int(ns.value)}
+        _lib.check(lib.s5d_batch_query(self._h, ctypes.byref(nl), ctypes.byref(ns)), "s5d_batch_query")
+        pl, wg, it = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(lib.s5d_batch_persistent_info(self._h, ctypes.byref(pl), ctypes.byref(wg), ctypes.byref(it)),
+                   "s5d_batch_persistent_info")
+        out = {"launches": int(nl.value), "round_steps": int(ns.value)}
+        if pl.value:
+            out.update(persistent_launches=int(pl.value), persistent_workgroups=int(wg.value),
+                       persistent_items=int(it.value))
+        return out
+
+    def status(self, stream=None):
+        """Synchronise the stream of the last run and raise Stencil5DError
+        (S5D_ETIMEDOUT) if a persistent launch's bounded wait ran out."""
+        handle = _stream_handle(stream, self._device) if self.n else 0
+        _lib.check(_lib.load().s5d_batch_status(self._h, ctypes.c_void_p(handle)), "s5d_batch_status")
+
+    def set_wait_limit(self, polls):
+        """Most polls a persistent workgroup waits for its grid's previous round."""
+        _lib.check(_lib.load().s5d_batch_set_wait_limit(self._h, int(polls)), "s5d_batch_set_wait_limit")
 
     def close(self):
         if getattr(self, "_h", None) is not None:

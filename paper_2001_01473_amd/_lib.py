@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libstencil5d.so")
 
-S5D_OK, S5D_EINVAL, S5D_EUNSUPPORTED, S5D_ENOMEM, S5D_EDEVICE, S5D_EBUDGET, S5D_ECANCELED = range(7)
+S5D_OK, S5D_EINVAL, S5D_EUNSUPPORTED, S5D_ENOMEM, S5D_EDEVICE, S5D_EBUDGET, S5D_ECANCELED, S5D_ETIMEDOUT = range(8)
 STAR, BOX = 0, 1
 F32, F64 = 0, 1
 ACC_PLAIN, ACC_COMPENSATED = 0, 1
@@ -25,7 +25,8 @@ EXPR_LINEAR, EXPR_DIV, EXPR_GRADIENT, EXPR_VARCOEF = range(4)
 
 # Every symbol include/stencil5d.h declares.
 EXPORTS = ("s5d_plan_create", "s5d_plan_destroy", "s5d_plan_query", "s5d_run", "s5d_run_fields",
-           "s5d_batch_create", "s5d_batch_run", "s5d_batch_query", "s5d_batch_destroy",
+           "s5d_batch_create", "s5d_batch_run", "s5d_batch_query", "s5d_batch_status",
+           "s5d_batch_set_wait_limit", "s5d_batch_persistent_info", "s5d_batch_destroy",
            "s5d_run_batch",
            "s5d_server_create", "s5d_server_destroy", "s5d_server_now", "s5d_server_submit",
            "s5d_server_tick", "s5d_server_cancel", "s5d_server_sync", "s5d_server_request", "s5d_server_fetch",
@@ -36,6 +37,7 @@ EXPORTS = ("s5d_plan_create", "s5d_plan_destroy", "s5d_plan_query", "s5d_run", "
            "s5d_status_string", "s5d_last_error")
 NORMS_COUNT = 5
 BATCH_GRAPH = 1
+BATCH_PERSISTENT = 2
 
 
 class S5DDesc(ctypes.Structure):
@@ -148,6 +150,13 @@ def load():
         lib.s5d_batch_run.argtypes = [vp, vp, i32p]
         lib.s5d_batch_query.restype = ctypes.c_int32
         lib.s5d_batch_query.argtypes = [vp, i32p, i32p]
+        lib.s5d_batch_status.restype = ctypes.c_int32
+        lib.s5d_batch_status.argtypes = [vp, vp]
+        lib.s5d_batch_set_wait_limit.restype = ctypes.c_int32
+        lib.s5d_batch_set_wait_limit.argtypes = [vp, ctypes.c_int64]
+        lib.s5d_batch_persistent_info.restype = ctypes.c_int32
+        lib.s5d_batch_persistent_info.argtypes = [vp, i32p, ctypes.POINTER(ctypes.c_int64),
+                                                  ctypes.POINTER(ctypes.c_int64)]
         lib.s5d_batch_destroy.restype = None
         lib.s5d_batch_destroy.argtypes = [vp]
         lib.s5d_run_batch.restype = ctypes.c_int32

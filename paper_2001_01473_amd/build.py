@@ -42,7 +42,8 @@ DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
                 "-I" + CSRC, "-I" + INCLUDE]
 
 HOST_SOURCES = ["abi.cpp", "batch.cpp", "server.cpp", "tune.cpp", "halo.hip", "norms.hip", "direct.hip"]
-HEADERS = ["s5d_internal.h", "kcommon.h", "sweep2d.h", "sweep3d.h", "sweepw2d.h"]
+HEADERS = ["s5d_internal.h", "kcommon.h", "sweep2d.h", "sweep3d.h", "sweepw2d.h", "sweepp2d.h", "persist2d.h",
+           "persist_schedule.h"]
 HOST_HEADERS = ["host.h", "batch.h", "norms.h", "direct.h", "stream2d.h", "stream3d.h"]  # not included by the variant units
 
 # Kernel kinds: (name, C++ type, 32-bit words per element, accumulation
@@ -64,6 +65,21 @@ EXPR_2D = [(1, 0, 1), (1, 0, 2), (1, 1, 1), (2, 0, 1), (3, 0, 1), (3, 0, 2), (3,
 # Deepest fused depth compiled per expression (window kernels keep 2r+1 rows
 # per level; per-cell weights add n loads per cell and level).
 MAX_BT_EXPR = {1: 10, 2: 10, 3: 4}
+
+
+# Persistent batched launches (sweepp2d.h): the 2D families that get one
+# kernel each, as (kind, box, r, cells per lane, deepest depth).  A family's
+# kernel holds every depth 1..deepest and takes the registers of the deepest,
+# so the deepest depth kept is the one whose own kernel still runs at the
+# occupancy of the family's default depth.
+PERSIST_2D = [(0, 0, 1, 4, 10), (0, 0, 2, 4, 7), (0, 1, 1, 4, 7), (1, 0, 1, 2, 10), (1, 0, 2, 2, 6)]
+# waves per SIMD asked of each family's kernel: that of its deepest depth alone
+PERSIST_WPE = {(0, 0, 1, 4, 10): 3, (0, 0, 2, 4, 7): 2, (0, 1, 1, 4, 7): 3, (1, 0, 1, 2, 10): 2, (1, 0, 2, 2, 6): 2}
+
+
+def _pname(f):
+    dtype, box, r, cpl, mx = f
+    return "kp2d_%s_%s_r%d_c%d_b%d" % (DTYPES[dtype][0], "box" if box else "star", r, cpl, mx)
 
 
 def est_vgprs_2d(words, box, r, cpl, bt, nr, accw=1):
@@ -248,10 +264,21 @@ def _write_if_changed(path, text):
         f.write(text)
 
 
-def _generate(variants, variants3=()):
+def _generate(variants, variants3=(), families=()):
     inst = os.path.join(BUILD, "inst")
     os.makedirs(inst, exist_ok=True)
     units = []
+    for f in families:
+        dtype, box, r, cpl, mx = f
+        depths = ", ".join("Depth<%d, %d>" % (bt, ring_depth(r, bt, DTYPES[dtype][2]))
+                           for bt in range(mx, 0, -1))
+        text = ('#include "sweepp2d.h"\nnamespace s5d {\nPersist2D %s() {\n'
+                '  return make_persist2d<%s, %d, 0, %d, %s, %d, %d, %s>();\n}\n}  // namespace s5d\n'
+                % (_pname(f), DTYPES[dtype][1], DTYPES[dtype][3], r, "true" if box else "false", cpl,
+                   PERSIST_WPE[f], depths))
+        path = os.path.join(inst, _pname(f) + ".hip")
+        _write_if_changed(path, text)
+        units.append(path)
     for v in variants3:
         dtype, expr, box, r, cpl, m, nw, bt, nr = v
         name = _vname3(v)
@@ -278,7 +305,7 @@ def _generate(variants, variants3=()):
         path = os.path.join(inst, name + ".hip")
         _write_if_changed(path, text)
         units.append(path)
-    lines = ['#include "s5d_internal.h"', "namespace s5d {"]
+    lines = ['#include "s5d_internal.h"', '#include "persist2d.h"', "namespace s5d {"]
     lines += ["Kernel2D %s();" % _vname(v) for v in variants]
     lines.append("const Entry2D kRegistry2D[] = {")
     for v in variants:
@@ -296,6 +323,15 @@ def _generate(variants, variants3=()):
         lines.append("  {0, 0, 0, 0, 0, 0, 0, 0, nullptr},")
     lines.append("};")
     lines.append("const int kRegistry3DSize = %d;" % len(variants3))
+    lines += ["Persist2D %s();" % _pname(f) for f in families]
+    lines.append("const EntryP2D kRegistryP2D[] = {")
+    for f in families:
+        dtype, box, r, cpl, mx = f
+        lines.append("  {%d, 0, %d, %d, %d, %d, &%s}," % (dtype, box, r, cpl, mx, _pname(f)))
+    if not families:
+        lines.append("  {0, 0, 0, 0, 0, 0, nullptr},")
+    lines.append("};")
+    lines.append("const int kRegistryP2DSize = %d;" % len(families))
     lines.append("}  // namespace s5d")
     reg = os.path.join(BUILD, "registry.cpp")
     _write_if_changed(reg, "\n".join(lines) + "\n")
@@ -350,7 +386,8 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
         shutil.rmtree(os.path.join(BUILD, "obj"))
     cands = [v for v in candidates_2d() if only is None or re.search(only, _vname(v))]
     cands3 = [v for v in candidates_3d() if only is None or re.search(only, _vname3(v))]
-    units, _ = _generate(cands, cands3)
+    fams = [f for f in PERSIST_2D if only is None or re.search(only, _pname(f))]
+    units, _ = _generate(cands, cands3, fams)
     # kernel units include only the device headers they use (a 3D unit does
     # not see the 2D sweep, and so on); host sources also the public header and
     # the host-side internal headers
@@ -360,12 +397,16 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
         "2d": _digest([os.path.join(CSRC, h) for h in base_hdr + ["sweep2d.h"]], []),
         "w2d": _digest([os.path.join(CSRC, h) for h in base_hdr + ["sweep2d.h", "sweepw2d.h"]], []),
         "3d": _digest([os.path.join(CSRC, h) for h in base_hdr + ["sweep3d.h"]], []),
+        "p2d": _digest([os.path.join(CSRC, h) for h in base_hdr + ["sweep2d.h", "sweepp2d.h", "persist2d.h",
+                                                                     "persist_schedule.h"]], []),
     }
 
     def key_of_unit(path):
         name = os.path.basename(path)
         if name.startswith("k3d_"):
             return unit_hdr["3d"]
+        if name.startswith("kp2d_"):
+            return unit_hdr["p2d"]
         if "_grad_" in name or "_varc_" in name:
             return unit_hdr["w2d"]
         return unit_hdr["2d"]
@@ -376,7 +417,7 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
     host_hdr = hdr + _digest([os.path.join(CSRC, h) for h in HOST_HEADERS] +
                              [os.path.join(INCLUDE, "stencil5d.h")], [])
     # longest first: the box and deep variants dominate the build time
-    order = sorted(units, key=lambda p: (("box" not in p), -len(p))) + host
+    order = sorted(units, key=lambda p: ("kp2d_" not in p, "box" not in p, -len(p))) + host
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         futs = {ex.submit(_compile, s, host_hdr if s in host else key_of_unit(s), incremental): s
                 for s in order}
@@ -398,15 +439,21 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
         r = dict(res_by_unit.get(_vname3(v), {}))
         r["ok"] = r.get("scratch", 1) == 0 and r.get("vgprs", 999) <= 256 and r.get("agprs", 0) <= 128
         record[_vname3(v)] = r
+    for f in fams:
+        r = dict(res_by_unit.get(_pname(f), {}))
+        r["ok"] = r.get("scratch", 1) == 0 and r.get("vgprs", 999) <= 256 and r.get("agprs", 0) <= 128
+        record[_pname(f)] = r
     kept = [v for v in cands if record[_vname(v)]["ok"]]
     kept3 = [v for v in cands3 if record[_vname3(v)]["ok"]]
-    _, reg = _generate(kept, kept3)
+    keptp = [f for f in fams if record[_pname(f)]["ok"]]
+    _, reg = _generate(kept, kept3, keptp)
     reg_obj, _, _ = _compile(reg, hdr, False)
     with open(RESOURCES, "w") as f:
         json.dump(record, f, indent=1, sort_keys=True)
     link = [objs[s] for s in host] + [reg_obj] + \
         [objs[os.path.join(BUILD, "inst", _vname(v) + ".hip")] for v in kept] + \
-        [objs[os.path.join(BUILD, "inst", _vname3(v) + ".hip")] for v in kept3]
+        [objs[os.path.join(BUILD, "inst", _vname3(v) + ".hip")] for v in kept3] + \
+        [objs[os.path.join(BUILD, "inst", _pname(f) + ".hip")] for f in keptp]
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *link]
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
@@ -414,8 +461,9 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
         raise RuntimeError("link failed:\n" + res.stdout)
     os.replace(tmp, LIB)
     if verbose:
-        print("built %s: %d of %d 2D and %d of %d 3D candidate variants fit in registers, %.0f s"
-              % (LIB, len(kept), len(cands), len(kept3), len(cands3), time.time() - t0))
+        print("built %s: %d of %d 2D and %d of %d 3D candidate variants and %d of %d persistent families fit "
+              "in registers, %.0f s" % (LIB, len(kept), len(cands), len(kept3), len(cands3), len(keptp),
+                                        len(fams), time.time() - t0))
     return LIB
 
 

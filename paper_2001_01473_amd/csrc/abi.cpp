@@ -486,6 +486,13 @@ int fill_round_item(const s5d_plan* p, int bt, const void* src, void* dst, void*
   return p->by_bt[bt].fill_item(item, rd);
 }
 
+int fill_persist_round(const s5d_plan* p, const Persist2D& k, int bt, const void* src, void* dst, void* out,
+                       int chunk, int grid, int need) {
+  Round2D rd = round2d(p, src, dst, nullptr);
+  if (chunk > 0) rd.chunk = chunk;
+  return k.fill_round(out, rd, bt, grid, need);
+}
+
 int shared_chunk(const s5d_plan* p, int bt, double share) {
   if (p->direct || !p->chunk_auto || p->d.ndim != 2 || bt < 1 || p->slots <= 0) return p->tun.stream_chunk;
   const int r = p->d.radius;
@@ -522,6 +529,7 @@ const char* s5d_status_string(s5d_status status) {
     case S5D_EDEVICE: return "S5D_EDEVICE";
     case S5D_EBUDGET: return "S5D_EBUDGET";
     case S5D_ECANCELED: return "S5D_ECANCELED";
+    case S5D_ETIMEDOUT: return "S5D_ETIMEDOUT";
     default: return "S5D_UNKNOWN";
   }
 }

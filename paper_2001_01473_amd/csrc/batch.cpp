@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -154,6 +155,26 @@ s5d_status check_disjoint(const std::vector<std::pair<uintptr_t, uintptr_t>>& ra
 
 }  // namespace s5d
 
+namespace s5d {
+namespace {
+// Persistent mode: one launch per stencil family, over its round table and
+// work items (byte offsets into the device blob) and its control block.
+struct FamilyLaunch {
+  Persist2D k;
+  size_t rounds_off = 0, items_off = 0, ctl_off = 0;
+  int32_t n_items = 0;
+  int nblocks = 0;
+};
+constexpr int64_t kDefaultWaitLimit = int64_t{1} << 24;
+// Shortest stream block of a library-chosen length in a persistent launch:
+// the queue balances the load by itself, and every work item pays an
+// agent-scope release and acquire, so fewer, longer blocks win (measured on
+// MI355X, 64-grid mix: 1117 GCell/s at the shared-launch lengths, 1356 with
+// this floor, 1335 at 512, 1007 at 1024).
+constexpr int kPersistMinChunk = 256;
+}  // namespace
+}  // namespace s5d
+
 struct s5d_batch {
   // boundary copies of every grid with work: one launch over a device table
   // of HaloItems at byte offset halo_off of the device blob
@@ -171,6 +192,13 @@ struct s5d_batch {
   bool graph = false;
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t exec = nullptr;
+  // persistent mode: the family launches and their control blocks (one
+  // contiguous int32 range of the blob, cleared before every run)
+  bool persistent = false;
+  std::vector<s5d::FamilyLaunch> families;
+  size_t ctl_off = 0;
+  int64_t ctl_ints = 0;
+  int64_t wait_limit = s5d::kDefaultWaitLimit;
 };
 
 namespace {
@@ -178,10 +206,39 @@ namespace {
 hipError_t enqueue_batch(const s5d_batch* b, hipStream_t st) {
   constexpr int kMaxHaloItems = 65535;  // grid y-dimension of the boundary-copy launch
   const s5d::HaloItem* halo = reinterpret_cast<const s5d::HaloItem*>(b->dev + b->halo_off);
+  if (b->persistent && b->ctl_ints > 0) {
+    const hipError_t e =
+        s5d::launch_fill_i32(reinterpret_cast<int32_t*>(b->dev + b->ctl_off), b->ctl_ints, 0, st);
+    if (e != hipSuccess) return e;
+  }
   for (int32_t i = 0; i < b->n_halo; i += kMaxHaloItems) {
     const hipError_t e = s5d::launch_halo_copy_batch(halo + i, std::min(kMaxHaloItems, b->n_halo - i),
                                                      b->halo_max_cells, st);
     if (e != hipSuccess) return e;
+  }
+  if (b->persistent) {
+    // families touch different grids: fork them over the side streams
+    const int nf = static_cast<int>(b->families.size());
+    const int nside = (b->ss.fork && nf >= 2) ? std::min(b->ss.n_side, nf - 1) : 0;
+    hipError_t e = hipSuccess;
+    if (nside > 0) {
+      if ((e = hipEventRecord(b->ss.fork, st)) != hipSuccess) return e;
+      for (int i = 0; i < nside; ++i)
+        if ((e = hipStreamWaitEvent(b->ss.side[i], b->ss.fork, 0)) != hipSuccess) return e;
+    }
+    for (int j = 0; j < nf; ++j) {
+      const s5d::FamilyLaunch& f = b->families[j];
+      const int q = nside > 0 ? j % (nside + 1) : 0;
+      e = f.k.launch(b->dev + f.rounds_off, reinterpret_cast<const s5d::PersistItem*>(b->dev + f.items_off),
+                     f.n_items, reinterpret_cast<int32_t*>(b->dev + f.ctl_off), b->wait_limit, f.nblocks,
+                     q == 0 ? st : b->ss.side[q - 1]);
+      if (e != hipSuccess) return e;
+    }
+    for (int i = 0; i < nside; ++i) {
+      if ((e = hipEventRecord(b->ss.join[i], b->ss.side[i])) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(st, b->ss.join[i], 0)) != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
   for (const auto& step : b->steps) {
     const hipError_t e = s5d::enqueue_step(step, b->dev, st, &b->ss);
@@ -203,6 +260,117 @@ void release(s5d_batch* b) {
 
 }  // namespace
 
+namespace s5d {
+
+// Persistent mode: group the grids by stencil family, lay out each family's
+// round table, work items and control block in `blob`, and size its launch.
+s5d_status build_persistent(s5d_batch* b, const s5d_plan* const* plans, void* const* buf0, void* const* buf1,
+                            int32_t n, const std::vector<std::vector<int>>& rounds, const std::vector<int>& chunks,
+                            const std::vector<double>& work, std::vector<unsigned char>& blob) {
+  // family of every grid with work
+  std::vector<int> fam(static_cast<size_t>(n), -1);
+  for (int32_t g = 0; g < n; ++g) {
+    if (rounds[g].empty()) continue;
+    const s5d_plan* p = plans[g];
+    const int box = p->d.shape == S5D_BOX ? 1 : 0;
+    if (p->d.ndim != 2 || p->direct)
+      return fail(S5D_EUNSUPPORTED, "grid " + std::to_string(g) + ": persistent batches run 2D blocked plans only");
+    const int bt_max = *std::max_element(rounds[g].begin(), rounds[g].end());
+    for (int i = 0; i < kRegistryP2DSize; ++i) {
+      const EntryP2D& e = kRegistryP2D[i];
+      if (e.dtype == p->kind && e.expr == p->expr && e.box == box && e.r == p->d.radius &&
+          e.cpl == p->tun.cells_per_lane && bt_max <= e.max_bt) {
+        fam[g] = i;
+        break;
+      }
+    }
+    if (fam[g] < 0)
+      return fail(S5D_EUNSUPPORTED, "grid " + std::to_string(g) + ": no persistent kernel for this stencil, "
+                                    "cells per lane and depth");
+  }
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+    (void)hipGetLastError();
+    cus = 256;
+  }
+  double total_work = 0;
+  for (int32_t g = 0; g < n; ++g)
+    if (fam[g] >= 0) total_work += work[g];
+  std::vector<unsigned char> tmp;
+  std::vector<size_t> ctl_offs;  // control blocks are laid out after every table
+  std::vector<int64_t> ctl_sizes;
+  for (int fi = 0; fi < kRegistryP2DSize; ++fi) {
+    std::vector<int32_t> members;
+    double fwork = 0;
+    for (int32_t g = 0; g < n; ++g)
+      if (fam[g] == fi) {
+        members.push_back(g);
+        fwork += work[g];
+      }
+    if (members.empty()) continue;
+    FamilyLaunch f;
+    f.k = kRegistryP2D[fi].make();
+    const size_t rb = static_cast<size_t>(f.k.round_bytes);
+    tmp.assign(rb + 16, 0);
+    void* scratch = reinterpret_cast<void*>(align_up(reinterpret_cast<uintptr_t>(tmp.data()), 16));
+    // workgroups of every round of every member (need is not known yet)
+    std::vector<std::vector<int32_t>> blocks(members.size());
+    std::vector<int> pchunk(static_cast<size_t>(n), 0);
+    for (int32_t g : members) pchunk[g] = plans[g]->chunk_auto ? std::max(chunks[g], kPersistMinChunk) : chunks[g];
+    for (size_t j = 0; j < members.size(); ++j) {
+      const int32_t g = members[j];
+      void* bufs[2] = {buf0[g], buf1[g]};
+      for (size_t k = 0; k < rounds[g].size(); ++k) {
+        const int nb = fill_persist_round(plans[g], f.k, rounds[g][k], bufs[k % 2], bufs[(k + 1) % 2], scratch,
+                                          pchunk[g], 0, 0);
+        if (nb <= 0) return fail(S5D_EUNSUPPORTED, "grid " + std::to_string(g) + ": round does not fit a launch");
+        blocks[j].push_back(nb);
+      }
+    }
+    std::vector<PersistRound> prounds;
+    std::vector<PersistItem> items;
+    if (!persist_schedule(blocks, kWavesPerBlock, prounds, items))
+      return fail(S5D_EUNSUPPORTED, "persistent work list exceeds 2^31 items");
+    f.rounds_off = align_up(blob.size(), 256);
+    blob.resize(f.rounds_off + prounds.size() * rb);
+    for (size_t i = 0; i < prounds.size(); ++i) {
+      const PersistRound& pr = prounds[i];
+      const int32_t g = members[pr.grid];
+      void* bufs[2] = {buf0[g], buf1[g]};
+      const int k = pr.round;
+      fill_persist_round(plans[g], f.k, rounds[g][k], bufs[k % 2], bufs[(k + 1) % 2], scratch, pchunk[g], pr.grid,
+                         pr.need);
+      std::memcpy(blob.data() + f.rounds_off + i * rb, scratch, rb);
+    }
+    f.items_off = align_up(blob.size(), 256);
+    blob.resize(f.items_off + items.size() * sizeof(PersistItem));
+    std::memcpy(blob.data() + f.items_off, items.data(), items.size() * sizeof(PersistItem));
+    f.n_items = static_cast<int32_t>(items.size());
+    // resident workgroups, shared with the other families by their work
+    int occ = f.k.occupancy ? f.k.occupancy() : 0;
+    if (occ <= 0) occ = 1;
+    const double share = total_work > 0 ? fwork / total_work : 1.0;
+    const int64_t slots = static_cast<int64_t>(cus) * occ;
+    f.nblocks = static_cast<int>(std::max<int64_t>(
+        1, std::min<int64_t>(f.n_items, static_cast<int64_t>(std::ceil(static_cast<double>(slots) * share)))));
+    ctl_sizes.push_back(kPersistCtl + static_cast<int64_t>(members.size()));
+    b->families.push_back(f);
+  }
+  // one contiguous control range for all families (cleared by one launch)
+  b->ctl_off = align_up(blob.size(), 256);
+  size_t off = b->ctl_off;
+  for (size_t j = 0; j < b->families.size(); ++j) {
+    b->families[j].ctl_off = off;
+    off += static_cast<size_t>(ctl_sizes[j]) * sizeof(int32_t);
+  }
+  b->ctl_ints = static_cast<int64_t>((off - b->ctl_off) / sizeof(int32_t));
+  blob.resize(off, 0);
+  return S5D_OK;
+}
+
+}  // namespace s5d
+
 using s5d::device_fail;
 using s5d::fail;
 
@@ -215,7 +383,7 @@ s5d_status s5d_batch_create(const s5d_plan* const* plans, void* const* buf0, voi
   *out = nullptr;
   if (n < 0) return fail(S5D_EINVAL, "n must be >= 0");
   if (n > 0 && (!plans || !buf0 || !buf1)) return fail(S5D_EINVAL, "plans, buf0 and buf1 must not be NULL");
-  if (flags & ~S5D_BATCH_GRAPH) return fail(S5D_EINVAL, "unknown flags");
+  if (flags & ~(S5D_BATCH_GRAPH | S5D_BATCH_PERSISTENT)) return fail(S5D_EINVAL, "unknown flags");
   std::vector<std::pair<uintptr_t, uintptr_t>> ranges;
   for (int32_t g = 0; g < n; ++g) {
     if (!plans[g]) return fail(S5D_EINVAL, "plans[" + std::to_string(g) + "] is NULL");
@@ -232,6 +400,7 @@ s5d_status s5d_batch_create(const s5d_plan* const* plans, void* const* buf0, voi
   s5d_batch* b = new (std::nothrow) s5d_batch;
   if (!b) return fail(S5D_ENOMEM, "batch allocation failed");
   b->graph = (flags & S5D_BATCH_GRAPH) != 0;
+  b->persistent = (flags & S5D_BATCH_PERSISTENT) != 0;
   std::vector<std::vector<int>> rounds(static_cast<size_t>(n));
   size_t kmax = 0;
   try {
@@ -279,6 +448,14 @@ s5d_status s5d_batch_create(const s5d_plan* const* plans, void* const* buf0, voi
       blob.resize(halos.size() * sizeof(s5d::HaloItem));
       std::memcpy(blob.data(), halos.data(), blob.size());
     }
+    if (b->persistent) {
+      const s5d_status st = s5d::build_persistent(b, plans, buf0, buf1, n, rounds, chunks, work, blob);
+      if (st != S5D_OK) {
+        release(b);
+        return st;
+      }
+      kmax = 0;  // no per-round-index steps
+    }
     b->steps.resize(kmax);
     for (size_t k = 0; k < kmax; ++k) {
       std::vector<s5d::RoundItem> items;
@@ -309,7 +486,7 @@ s5d_status s5d_batch_create(const s5d_plan* const* plans, void* const* buf0, voi
         release(b);
         return device_fail(e, "upload of the batch tables");
       }
-      size_t widest = 1;
+      size_t widest = std::max<size_t>(1, b->families.size());
       for (const auto& step : b->steps) widest = std::max(widest, step.size());
       if (widest >= 2) {
         e = b->ss.create(static_cast<int>(std::min<size_t>(widest - 1, s5d::kMaxSideStreams)));
@@ -371,9 +548,53 @@ s5d_status s5d_batch_query(const s5d_batch* batch, int32_t* n_launches, int32_t*
   s5d::clear_error();
   if (!batch) return fail(S5D_EINVAL, "batch is NULL");
   int32_t nl = (batch->n_halo + 65534) / 65535;
+  if (batch->persistent && batch->ctl_ints > 0) nl += 1 + static_cast<int32_t>(batch->families.size());
   for (const auto& s : batch->steps) nl += static_cast<int32_t>(s.size());
   if (n_launches) *n_launches = nl;
   if (n_round_steps) *n_round_steps = static_cast<int32_t>(batch->steps.size());
+  return S5D_OK;
+}
+
+s5d_status s5d_batch_persistent_info(const s5d_batch* batch, int32_t* n_launches, int64_t* workgroups,
+                                     int64_t* items) {
+  s5d::clear_error();
+  if (!batch) return fail(S5D_EINVAL, "batch is NULL");
+  int64_t wg = 0, it = 0;
+  for (const s5d::FamilyLaunch& f : batch->families) {
+    wg += f.nblocks;
+    it += f.n_items;
+  }
+  if (n_launches) *n_launches = static_cast<int32_t>(batch->families.size());
+  if (workgroups) *workgroups = wg;
+  if (items) *items = it;
+  return S5D_OK;
+}
+
+s5d_status s5d_batch_status(s5d_batch* batch, void* stream) {
+  s5d::clear_error();
+  if (!batch) return fail(S5D_EINVAL, "batch is NULL");
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "hipStreamSynchronize");
+  for (const s5d::FamilyLaunch& f : batch->families) {
+    int32_t ctl[2] = {0, 0};
+    e = hipMemcpy(ctl, batch->dev + f.ctl_off, sizeof(ctl), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_fail(e, "reading the persistent launch status");
+    if (ctl[1] != 0) return fail(S5D_ETIMEDOUT, "a workgroup's wait for its grid's previous round ran out");
+  }
+  return S5D_OK;
+}
+
+s5d_status s5d_batch_set_wait_limit(s5d_batch* batch, int64_t polls) {
+  s5d::clear_error();
+  if (!batch) return fail(S5D_EINVAL, "batch is NULL");
+  if (polls < 0) return fail(S5D_EINVAL, "polls must be >= 0");
+  batch->wait_limit = polls;
+  if (batch->exec) {
+    // the limit is a kernel argument of the captured launches: capture again
+    (void)hipDeviceSynchronize();
+    (void)hipGraphExecDestroy(batch->exec);
+    batch->exec = nullptr;
+  }
   return S5D_OK;
 }
 

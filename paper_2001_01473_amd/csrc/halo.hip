@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "persist2d.h"
 #include "s5d_internal.h"
 
 namespace s5d {
@@ -81,7 +82,22 @@ __global__ void halo_copy_batch_kernel(const HaloItem* __restrict__ items) {
                     h.r, r2, t0, stride);
 }
 
+__global__ void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
 }  // namespace
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int threads = 256;
+  int64_t blocks = (n + threads - 1) / threads;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(static_cast<unsigned>(blocks)), dim3(threads), 0, stream, p, n, v);
+  return hipGetLastError();
+}
 
 hipError_t launch_halo_copy(const void* src, void* dst, int elem_bytes, int ndim, const int64_t* padded, int r,
                             hipStream_t stream) {

@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "persist2d.h"
 #include "s5d_internal.h"
 #include "stencil5d.h"
 
@@ -56,6 +57,12 @@ struct BatchHooks {
 BatchHooks batch_hooks(const s5d_plan* p, int bt);
 // Write p's batch item for a round into `item`; returns its workgroups.
 int fill_round_item(const s5d_plan* p, int bt, const void* src, void* dst, void* item, int chunk = 0);
+
+// Write the persistent-launch round table entry of one round of p (depth bt,
+// family kernel k) into `out`; returns the round's workgroups (0: too large,
+// -1: the family has no kernel of that depth).
+int fill_persist_round(const s5d_plan* p, const Persist2D& k, int bt, const void* src, void* dst, void* out,
+                       int chunk, int grid, int need);
 
 // Stream-block length for a grid that shares each launch with others and
 // gets about `share` (0 < share <= 1) of the machine's workgroup slots: the
