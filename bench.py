@@ -880,6 +880,53 @@ def model_accuracy(md=None, kinds=(0, 1), top=5):
     return summary
 
 
+def write_tuning(path, top_k=5, steps=200):
+    """Autotune (s5d_autotune, model-ranked, top_k measured) every stencil of
+    the benchmark suite at the benchmark sizes -- the six 2D stencils at
+    16384^2 and the 3D stars and boxes of radius 1 and 2 at 512^3, in float32,
+    float64 and compensated float32, and the expression stencils of Table 3 --
+    and save the winners as the library's shipped tuning file."""
+    import paper_2001_01473_amd as s5d
+    s5d.tune_cache_clear()
+    cases = []
+    for kind in (0, 1, 2):
+        for r, box in STENCILS:
+            cases.append((2, r, box, kind, "linear", (N, N)))
+        for r in (1, 2):
+            for box in (False, True):
+                cases.append((3, r, box, kind, "linear", (N3, N3, N3)))
+    for name, nd, r, box, expr, _, _, _ in EXPR_CASES:
+        for kind in (0, 1):
+            cases.append((nd, r, box, kind, expr, (N, N) if nd == 2 else (N3, N3, N3)))
+    for nd, r, box, kind, expr, interior in cases:
+        dtype, accum = KINDS[kind]
+        n = si.n_points(nd, r, box)
+        c = si.random_coeffs(np.random.default_rng(si.workload_seed(1)), n)
+        if expr == "div":
+            c = np.append(c, 1.0)
+        elif expr == "gradient":
+            c = np.array([0.5, 1.0])
+        elif expr == "varcoef":
+            c = None
+        try:
+            tun, rep = s5d.autotune(ndim=nd, radius=r, box=box, dtype=dtype, interior=interior, steps=steps,
+                                    coeffs=c, accum=accum, expr=expr, top_k=top_k)
+        except Exception as e:  # noqa: BLE001 - reported, not fatal
+            print(json.dumps({"ndim": nd, "r": r, "box": box, "kind": KIND_NAMES[kind], "expr": expr,
+                              "error": str(e)[:120]}), flush=True)
+            continue
+        print(json.dumps({"ndim": nd, "r": r, "box": box, "kind": KIND_NAMES[kind], "expr": expr,
+                          "bt": tun["bt"], "stream_chunk": tun["stream_chunk"],
+                          "best_s_per_step": rep["best_seconds_per_step"],
+                          "default_s_per_step": rep["default_seconds_per_step"]}), flush=True)
+    s5d.tune_cache_save(path)
+    text = open(path).read()
+    with open(path, "w") as f:
+        f.write("# written by: python bench.py --write-tuning <this file>  (s5d_autotune, top %d measured, "
+                "T = %d, on MI355X)\n" % (top_k, steps))
+        f.write(text)
+
+
 def summarize_pmc(d, kernel):
     """Markdown table of per-dispatch counter averages (rocprofv3 --pmc CSV)."""
     import csv
@@ -1010,10 +1057,14 @@ def main(argv=None):
     ap.add_argument("--accuracy-full", nargs="?", const="all", choices=("all", "2d", "3d"),
                     help="compare whole T = 1000 grids at the benchmark sizes with the CPU oracle")
     ap.add_argument("--expr", action="store_true", help="time only the expression stencils")
+    ap.add_argument("--write-tuning", default=None, metavar="PATH",
+                    help="autotune the benchmark suite and save the library's tuning file")
     ap.add_argument("--model-accuracy", action="store_true",
                     help="predicted against measured time of every blocked variant (with --md: a table)")
     ap.add_argument("--model-kinds", default="0,1", help="with --model-accuracy: kinds (0 f32, 1 f64, 2 f32c)")
     ap.add_argument("--md", default=None, help="with --accuracy-full: write a markdown table here")
+    ap.add_argument("--acc-stencils", default=None,
+                    help="with --accuracy-full: comma-separated 2D stencils (e.g. star2d1r,box2d2r)")
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-loads", default="0.5,0.9")
     ap.add_argument("--serve-budgets-gib", default="64")
@@ -1056,8 +1107,16 @@ def main(argv=None):
         print(json.dumps(sweep_expr()))
         return 0
     if args.accuracy_full:
-        rows = accuracy_full(args.accuracy_full, args.md)
+        sel = STENCILS
+        if args.acc_stencils:
+            names = args.acc_stencils.split(",")
+            sel = [(r, box) for r, box in STENCILS if stencil_name(r, box) in names]
+        rows = accuracy_full(args.accuracy_full, args.md, stencils2d=sel)
         return 0 if all(r["ok"] for r in rows) else 1
+    if args.write_tuning:
+        os.environ["S5D_TUNING_FILE"] = ""  # measure against the built-in defaults
+        write_tuning(args.write_tuning)
+        return 0
     if args.model_accuracy:
         model_accuracy(args.md, kinds=tuple(int(k) for k in args.model_kinds.split(",")))
         return 0

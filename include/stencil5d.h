@@ -229,14 +229,20 @@ typedef struct s5d_tune_report {
  * lengths, rank them by the model, time the best top_k on the GPU (two full
  * rounds each, on scratch buffers the tuner allocates and frees), and keep
  * the fastest, or the library's default if none beats it.  top_k = 0 trusts
- * the model alone.  The winner goes to *best and into the process-wide cache,
+ * the model alone.  The winner goes to *best and, unless it is the choice a
+ * plan without tuning gets already, into the process-wide cache,
  * from which s5d_plan_create takes it whenever it is given no tuning for a
  * descriptor with the same stencil, dtype, accumulation and power-of-two
  * bucket of every extent.  Synchronous on `stream`. */
 s5d_status s5d_autotune(const s5d_desc *desc, int32_t top_k, void *stream, s5d_tuning *best,
                         s5d_tune_report *report);
 
-/* Write / merge / empty the tuning cache (a small text file, one entry per line). */
+/* Write / merge / empty the tuning cache (a small text file, one entry per line).
+ * The first s5d_plan_create of a process merges the autotuner's choices
+ * measured on MI355X at the benchmark sizes into the cache: the file
+ * tuning_gfx950.txt beside the library, or the file the environment variable
+ * S5D_TUNING_FILE names (an empty value: none).  A missing or malformed file
+ * leaves the library's built-in defaults in place. */
 s5d_status s5d_tune_cache_save(const char *path);
 s5d_status s5d_tune_cache_load(const char *path);
 void s5d_tune_cache_clear(void);

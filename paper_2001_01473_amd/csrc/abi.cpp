@@ -640,6 +640,7 @@ s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_p
   // is taken if one is cached and still valid; else the library's defaults
   s5d_tuning cached;
   s5d_status st = S5D_EINVAL;
+  s5d::load_default_tuning();
   if (!tuning && s5d::tune_cache_lookup(d, &cached)) {
     st = d.ndim == 2 ? plan_2d(p, cached, box, r) : plan_3d(p, cached, box, r);
     if (st != S5D_OK) {

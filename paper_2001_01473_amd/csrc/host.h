@@ -83,4 +83,8 @@ s5d_status model_plan(const s5d_plan* p, s5d_model* out);
 // accumulation and extent bucket, if any.
 bool tune_cache_lookup(const s5d_desc& d, s5d_tuning* tun);
 
+// Load the autotuner's shipped choices once per process: the file named by
+// S5D_TUNING_FILE (empty: none), else tuning_gfx950.txt beside the library.
+void load_default_tuning();
+
 }  // namespace s5d

@@ -11,11 +11,14 @@
 // exchange.  The tuner enumerates the compiled variants and a set of stream
 // block lengths, ranks them by the model, measures the best few on the GPU and
 // caches the winner per (stencil, dtype, accumulation, extent bucket).
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
+#include <string>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -289,6 +292,30 @@ std::map<Key, CacheEntry> g_cache;
 
 }  // namespace
 
+void load_default_tuning() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    std::string path;
+    if (const char* env = std::getenv("S5D_TUNING_FILE")) {
+      path = env;  // an empty value disables the file
+    } else {
+      Dl_info info;
+      if (dladdr(reinterpret_cast<void*>(&load_default_tuning), &info) && info.dli_fname) {
+        const std::string so = info.dli_fname;
+        const size_t slash = so.rfind('/');
+        path = (slash == std::string::npos ? std::string(".") : so.substr(0, slash)) + "/tuning_gfx950.txt";
+      }
+    }
+    if (path.empty()) return;
+    if (FILE* f = std::fopen(path.c_str(), "r")) {
+      std::fclose(f);
+      // a malformed file leaves the library's own defaults in place
+      (void)s5d_tune_cache_load(path.c_str());
+      clear_error();
+    }
+  });
+}
+
 bool tune_cache_lookup(const s5d_desc& d, s5d_tuning* tun) {
   std::lock_guard<std::mutex> lk(g_cache_mu);
   auto it = g_cache.find(key_of(d));
@@ -442,6 +469,7 @@ s5d_status s5d_autotune(const s5d_desc* desc, int32_t top_k, void* stream, s5d_t
   cands.swap(uniq);
 
   Candidate* win = &cands[0];
+  bool base_won = false;
   double base_measured = -1;
   int n_measured = 0;
   if (top_k > 0 && desc->steps > 0) {
@@ -488,10 +516,12 @@ s5d_status s5d_autotune(const s5d_desc* desc, int32_t top_k, void* stream, s5d_t
       // the library's own choice stays if no candidate beats it
       cands.push_back(Candidate{base_tun, 0.0, base_measured});
       win = &cands.back();
+      base_won = true;
     }
   }
   *best = win->tun;
-  {
+  if (!base_won) {
+    // (the library's own choice needs no entry: plans without one get it)
     std::lock_guard<std::mutex> lk(s5d::g_cache_mu);
     s5d::g_cache[s5d::key_of(*desc)] =
         s5d::CacheEntry{win->tun, win->measured, {desc->interior[0], desc->interior[1], desc->interior[2]}};
