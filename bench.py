@@ -997,6 +997,55 @@ PROBE_BT = 10
 PROBE_COPY_BYTES = 1 << 30
 
 
+def bt_traffic(d, out_md, command):
+    """HBM traffic of the star2d1r float32 16384^2 launch for every b_T, from
+    rocprofv3 --pmc runs of `bench.py --probe --bt k` in d/FETCH_SIZE_bt<k> and
+    d/WRITE_SIZE_bt<k>; each counter is scaled by what it reads for the probe's
+    copy of known size.  The kernel of a run is the one other than the copy
+    with the most dispatches (the row-streaming kernel at b_T = 1)."""
+    import csv
+    import glob
+
+    def is_copy(k):
+        return "add" in k.lower() and "s5d" not in k
+
+    def load(path, counter):
+        per = {}
+        for f in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] == counter:
+                    per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        copy = [max(v) for k, v in per.items() if is_copy(k)]
+        kern = sorted(((len(v), k) for k, v in per.items() if not is_copy(k)), reverse=True)
+        if not copy or not kern:
+            raise SystemExit("no %s records in %s" % (counter, path))
+        name = kern[0][1]
+        return sum(per[name]) / len(per[name]), max(copy), name
+
+    rows = []
+    algo = 2.0 * 4 * N * N
+    for bt in range(1, 11):
+        try:
+            kf, cf, name = load(os.path.join(d, "FETCH_SIZE_bt%d" % bt), "FETCH_SIZE")
+            kw, cw, _ = load(os.path.join(d, "WRITE_SIZE_bt%d" % bt), "WRITE_SIZE")
+        except SystemExit as e:
+            print(e, file=sys.stderr)
+            continue
+        rd = kf * PROBE_COPY_BYTES / cf
+        wr = kw * PROBE_COPY_BYTES / cw
+        rows.append((bt, name.split("(")[0][:60], rd, wr, (rd + wr) / algo))
+    with open(out_md, "w") as f:
+        f.write("# HBM traffic per launch against b_T: star2d1r float32, 16384^2 interior\n\n")
+        f.write("Commands (from the repository root):\n\n```\n%s\n```\n\n" % command)
+        f.write("Each counter is scaled by what it reads for a copy of %d MiB each way.  Algorithmic bytes "
+                "per launch: one read and one write of the interior, %.3e.\n\n" % (PROBE_COPY_BYTES >> 20, algo))
+        f.write("| b_T | kernel | read bytes | write bytes | (read + write) / algorithmic |\n"
+                "|---|---|---|---|---|\n")
+        for bt, name, rd, wr, ratio in rows:
+            f.write("| %d | `%s` | %.3e | %.3e | %.2f |\n" % (bt, name, rd, wr, ratio))
+    return rows
+
+
 def probe(args):
     """Launches for rocprofv3 counter runs: a copy of known size, then the kernel."""
     import torch
@@ -1016,9 +1065,16 @@ def probe(args):
     b0 = torch.full(shape, 0.5, dtype=torch.float32, device="cuda:0")
     b1 = torch.empty_like(b0)
     # 2*b_T steps = two launches of the b_T kernel per run
-    tuning = {"bt": args.bt} if nd == 2 else {}
-    bt = args.bt if nd == 2 else s5d.Plan(ndim=3, radius=1, box=False, dtype="f32", interior=interior,
-                                          steps=1000, coeffs=np.full(7, 1 / 7)).query()["bt"]
+    if nd == 2 and args.bt:
+        tuning, bt = {"bt": args.bt}, args.bt
+    else:
+        # the launch of the default plan of the 1000-step sweep (the headline's)
+        ref = s5d.Plan(ndim=nd, radius=1, box=False, dtype="f32", interior=interior, steps=T_STEPS,
+                       coeffs=np.full(si.n_points(nd, 1, False), 1.0 / si.n_points(nd, 1, False)))
+        q = ref.query()
+        ref.close()
+        bt = q["bt"]
+        tuning = {k: q[k] for k in ("bt", "cells_per_lane", "stream_chunk")} if nd == 2 else {}
     plan = s5d.Plan(ndim=nd, radius=1, box=False, dtype="f32", interior=interior, steps=2 * bt,
                     coeffs=si.random_coeffs(np.random.default_rng(si.workload_seed(nd - 1)),
                                             si.n_points(nd, 1, False)), **tuning)
@@ -1076,9 +1132,14 @@ def main(argv=None):
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs of --probe into the traffic record")
     ap.add_argument("--command", default="", help="command line recorded with --ingest-counters")
+    ap.add_argument("--bt-traffic", nargs=2, metavar=("DIR", "OUT_MD"),
+                    help="per-b_T HBM traffic table from rocprofv3 --pmc runs of --probe --bt k")
     args = ap.parse_args(argv)
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
+        return 0
+    if args.bt_traffic:
+        bt_traffic(args.bt_traffic[0], args.bt_traffic[1], args.command)
         return 0
     if args.ingest_counters:
         ingest_counters(args.ingest_counters[0], args.ingest_counters[1], TRAFFIC_RECORD,
@@ -1093,8 +1154,6 @@ def main(argv=None):
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     if args.probe:
-        if args.bt == 0:
-            args.bt = PROBE_BT
         probe(args)
         return 0
     if args.full_sweep:

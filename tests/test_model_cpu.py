@@ -149,3 +149,54 @@ def test_model_ranking_prefers_deep_blocking_for_low_order_star():
                             interior=(16384, 16384), steps=1000, coeffs=np.full(5, 0.2))
     assert tun["bt"] >= 4
     s5d.tune_cache_clear()
+
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+_DEFAULT_FILE_SNIPPET = r"""
+import sys
+sys.path.insert(0, %r)
+import numpy as np
+import paper_2001_01473_amd as s5d
+p = s5d.Plan(ndim=2, radius=1, box=False, dtype="f64", interior=(16384, 16384), steps=1000,
+             coeffs=np.full(5, 0.2))
+print(p.query()["bt"], p.query()["cells_per_lane"])
+"""
+
+
+def _default_bt_with(env_value, tmp_path):
+    import os
+    import subprocess
+    import sys
+    env = dict(os.environ)
+    if env_value is None:
+        env.pop("S5D_TUNING_FILE", None)
+    else:
+        env["S5D_TUNING_FILE"] = env_value
+    out = subprocess.run([sys.executable, "-c", _DEFAULT_FILE_SNIPPET % ROOT], env=env, capture_output=True,
+                         text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    bt, cpl = out.stdout.split()
+    return int(bt), int(cpl)
+
+
+def test_tuning_file_is_merged_at_the_first_plan(tmp_path):
+    """The first plan of a process takes the entries of S5D_TUNING_FILE; an
+    empty value keeps the built-in defaults."""
+    f = tmp_path / "tuning.txt"
+    # star, r = 1, float64, plain, linear, buckets 14 x 14: b_T 3, 4 cells per lane
+    f.write_text("# test entry\n2 0 1 1 0 0 14 14 0 : 3 0 0 0 4 0 : 0.001 : 16384 16384 1\n")
+    assert _default_bt_with(str(f), tmp_path) == (3, 4)
+    builtin = _default_bt_with("", tmp_path)
+    assert builtin != (3, 4) and builtin[0] >= 1
+
+
+def test_shipped_tuning_file_parses():
+    import os
+    import paper_2001_01473_amd as s5d
+    path = os.path.join(ROOT, "paper_2001_01473_amd", "tuning_gfx950.txt")
+    if not os.path.exists(path):
+        pytest.skip("no shipped tuning file")
+    s5d.tune_cache_clear()
+    s5d.tune_cache_load(path)
+    s5d.tune_cache_clear()
