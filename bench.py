@@ -540,6 +540,37 @@ def bench_batch(reps=2):
                 batch.status()
                 out["launches_persistent"] = batch.query()["launches"]
                 batch.close()
+            # b_T, tile and h_SN from the autotuner, once per (radius, extent
+            # bucket) key; plans made afterwards take the cached choices
+            import math
+
+            def bucket(x):
+                return 0 if x <= 1 else int(math.ceil(math.log2(x)))
+            keys = {}
+            t0 = time.perf_counter()
+            for spec in specs:
+                key = (spec["radius"],) + tuple(bucket(x) for x in spec["interior"])
+                if key not in keys:
+                    rng = np.random.default_rng(spec["seed"])
+                    c = si.random_coeffs(rng, si.n_points(2, spec["radius"], False))
+                    keys[key] = s5d.autotune(ndim=2, radius=spec["radius"], box=False, dtype=dtype,
+                                             interior=spec["interior"], steps=spec["steps"], coeffs=c,
+                                             top_k=4)[0]["bt"]
+            out["autotune_keys"] = len(keys)
+            out["autotune_seconds"] = time.perf_counter() - t0
+            tuned = [_plan_for(s, dtype) for s in specs]
+            out["autotuned_bt_histogram"] = {str(b): sum(1 for p in tuned if p.query()["bt"] == b)
+                                             for b in sorted({p.query()["bt"] for p in tuned})}
+            batch = s5d.Batch(tuned, b0, b1, graph=True)
+            res["batched_autotuned_graph"] = _timed(batch.run, reset, reps)
+            batch.close()
+            for p in tuned:
+                p.close()
+            # leave the process's cache as it was: the shipped choices only
+            s5d.tune_cache_clear()
+            shipped = os.path.join(ROOT, "paper_2001_01473_amd", "tuning_gfx950.txt")
+            if os.path.exists(shipped) and os.environ.get("S5D_TUNING_FILE") is None:
+                s5d.tune_cache_load(shipped)
             out["launches_sequential"] = sum(
                 1 + -(-p.steps // p.query()["bt"]) for p in plans)
         for k, sec in res.items():
@@ -927,6 +958,32 @@ def write_tuning(path, top_k=5, steps=200):
         f.write(text)
 
 
+def summarize_trace(d, top=12):
+    """Markdown table of per-kernel dispatch durations from a rocprofv3
+    --kernel-trace run (its *kernel_trace.csv): calls, total, mean, median,
+    min, max, share of all kernel time; kernel names shortened to their
+    template arguments."""
+    import csv
+    import glob
+    import re
+    dur = {}
+    for f in glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            name = r["Kernel_Name"]
+            m = re.match(r"(?:void )?(?:s5d::)?([A-Za-z0-9_]+)(<[^()]*>)?", name)
+            short = (m.group(1) + (m.group(2) or "")) if m else name[:60]
+            dur.setdefault(short, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in dur.values())
+    rows = sorted(dur.items(), key=lambda kv: -sum(kv[1]))[:top]
+    print("| kernel | calls | total (ms) | mean (us) | median (us) | min (us) | max (us) | share |")
+    print("|---|---|---|---|---|---|---|---|")
+    for k, v in rows:
+        v = sorted(v)
+        print("| `%s` | %d | %.2f | %.1f | %.1f | %.1f | %.1f | %.1f%% |" % (
+            k, len(v), sum(v) / 1e3, sum(v) / len(v), v[len(v) // 2], v[0], v[-1], 100.0 * sum(v) / total))
+    return rows
+
+
 def summarize_pmc(d, kernel):
     """Markdown table of per-dispatch counter averages (rocprofv3 --pmc CSV)."""
     import csv
@@ -1132,9 +1189,14 @@ def main(argv=None):
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs of --probe into the traffic record")
     ap.add_argument("--command", default="", help="command line recorded with --ingest-counters")
+    ap.add_argument("--summarize-trace", default=None, metavar="DIR",
+                    help="per-kernel duration table of a rocprofv3 --kernel-trace run")
     ap.add_argument("--bt-traffic", nargs=2, metavar=("DIR", "OUT_MD"),
                     help="per-b_T HBM traffic table from rocprofv3 --pmc runs of --probe --bt k")
     args = ap.parse_args(argv)
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return 0
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
         return 0
