@@ -68,8 +68,9 @@ const Entry3D* find3d(int kind, int expr, int box, int r, int cpl, int m, int nw
   return nullptr;
 }
 
-// 3D defaults: depth and rows per wave (tile family), the best pair measured
-// on MI355X at 512^3, T = 1000, and a floor on the stream-block length where
+// 3D defaults: depth and rows per wave (tile family: 2 rows per wave is the
+// 16-wave tile, 4 the 8-wave one), the best pair measured on MI355X at 512^3,
+// T = 1000, and a floor on the stream-block length where
 // the measured optimum lies above the chooser's pick (the float32 27-point
 // box: 64 planes, 620 GCell/s against 566 at the chooser's 19).  Compensated
 // accumulation is bound by arithmetic from the first level on.
@@ -84,7 +85,7 @@ Default3D default_tuning3(int kind, int box, int r, int expr = 0) {
     if (r == 1) return box ? Default3D{2, 4} : Default3D{3, 2};
     return box ? Default3D{1, 2} : Default3D{2, 2};
   }
-  if (r == 1) return box ? Default3D{2, 4, 64} : Default3D{3, 4};
+  if (r == 1) return box ? Default3D{2, 4, 64} : Default3D{3, 2};
   return box ? Default3D{1, 4} : Default3D{2, 4};
 }
 int default_bt3(int kind, int box, int r, int expr) { return default_tuning3(kind, box, r, expr).bt; }

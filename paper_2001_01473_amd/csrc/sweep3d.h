@@ -101,6 +101,23 @@ __device__ __forceinline__ void sweep3d_body(const Sweep3DArgs& a, const CoefPac
     });
   };
 
+  // Folded lane shifts (float32 stars): the centre row's axis-2 terms that
+  // read a neighbouring lane take it through the FMA's DPP operand, with the
+  // coefficient in a VGPR.
+  constexpr bool FOLD = ACC == 0 && std::is_same_v<T, float> && !BOX;
+  T cv[2 * R + 1];
+  if constexpr (FOLD)
+    sfor<2 * R + 1>([&](auto D2) S5D_INL {
+      if constexpr (decltype(D2)::value != R) cv[D2] = to_vgpr(cf.c[2 * R + D2]);
+    });
+  // the same for the 27-point box: every row's axis-2 terms at d2 = -1, +1
+  constexpr bool FOLDB = ACC == 0 && std::is_same_v<T, float> && BOX && R == 1;
+  T cvb[FOLDB ? 27 : 1];
+  if constexpr (FOLDB)
+    sfor<27>([&](auto CI) S5D_INL {
+      if constexpr (decltype(CI)::value % 3 != 1) cvb[CI] = to_vgpr(cf.c[CI]);
+    });
+
   // Only levels below BT pass values on: the last level is stored, and the
   // boundary is never stored, so it needs no pass-through.
   constexpr int NCEN = BT > 1 ? BT - 1 : 1;
@@ -182,9 +199,18 @@ __device__ __forceinline__ void sweep3d_body(const Sweep3DArgs& a, const CoefPac
             sfor<2 * R + 1>([&](auto D1) S5D_INL {
               sfor<2 * R + 1>([&](auto D2) S5D_INL {
                 constexpr int ci = ((d0 + R) * (2 * R + 1) + D1) * (2 * R + 1) + D2;
-                const T v = X[MI + D1][K + D2];
-                if constexpr (first && D1 == 0 && D2 == 0) acc_k.first(cf.c[ci], v);
-                else acc_k.add(cf.c[ci], v);
+                constexpr int e = decltype(K)::value + decltype(D2)::value;  // extended column
+                constexpr bool lead = first && D1 == 0 && D2 == 0;
+                if constexpr (FOLDB && (e < R || e >= R + CPL)) {
+                  constexpr bool shr = e < R;
+                  constexpr int src = shr ? CPL - R + e : e - R - CPL;
+                  if constexpr (lead) acc_k.s = mul_dpp<shr>(X[MI + D1][R + src], cvb[ci]);
+                  else acc_k.s = fma_dpp<shr>(acc_k.s, X[MI + D1][R + src], cvb[ci]);
+                } else {
+                  const T v = X[MI + D1][K + D2];
+                  if constexpr (lead) acc_k.first(cf.c[ci], v);
+                  else acc_k.add(cf.c[ci], v);
+                }
               });
             });
           } else if constexpr (d0 != 0) {
@@ -195,7 +221,16 @@ __device__ __forceinline__ void sweep3d_body(const Sweep3DArgs& a, const CoefPac
           } else {
             // centre plane: (0,d1,0) d1<0, then (0,0,d2), then (0,d1,0) d1>0
             sfor<R>([&](auto J) S5D_INL { acc_k.add(cf.c[R + J], X[MI + J][R + K]); });
-            sfor<2 * R + 1>([&](auto D2) S5D_INL { acc_k.add(cf.c[2 * R + D2], X[R + MI][K + D2]); });
+            sfor<2 * R + 1>([&](auto D2) S5D_INL {
+              constexpr int e = decltype(K)::value + decltype(D2)::value;  // extended column
+              if constexpr (FOLD && (e < R || e >= R + CPL)) {
+                constexpr bool shr = e < R;  // from lane l-1, else lane l+1
+                constexpr int src = shr ? CPL - R + e : e - R - CPL;
+                acc_k.s = fma_dpp<shr>(acc_k.s, X[R + MI][R + src], cv[D2]);
+              } else {
+                acc_k.add(cf.c[2 * R + D2], X[R + MI][K + D2]);
+              }
+            });
             sfor<R>([&](auto J) S5D_INL { acc_k.add(cf.c[4 * R + 1 + J], X[R + MI + 1 + J][R + K]); });
           }
         };
