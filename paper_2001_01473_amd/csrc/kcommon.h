@@ -120,9 +120,12 @@ __device__ __forceinline__ double ieee_sqrt(double x) { return __builtin_sqrt(x)
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// Cache policy of the kernels' stores (the buffer instructions' aux operand;
-// 0 = default).
-constexpr int kStoreAux = 0;
+// Cache policy of the kernels' stores (the buffer instructions' aux operand):
+// non-temporal (nt), as a round's output is read only by the next launch.
+// Measured on MI355X against the default policy: +0.6 % for the headline
+// launch, +0.8 % for batched rounds, +3 % for the persistent batch (whose
+// per-item L2 write-back has less to write).
+constexpr int kStoreAux = 2;
 
 // Buffer descriptors (gfx9 family: 3rd dword 0x00020000, raw byte
 // addressing).  An access whose byte offset is >= nbytes reads 0 / is dropped.
