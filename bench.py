@@ -341,20 +341,25 @@ def full_sweep3d(only=None, direct=True):
 
 def sweep3d_default():
     """Every 3D stencil of the synthetic suite at 512^3, T = 1000, default plan;
-    the 7-point star and the 27-point box also with compensated float32."""
+    the 7-point star and the 27-point box also with compensated float32; the
+    radius-3 and radius-4 stars and boxes (one step per launch), the boxes over
+    100 steps."""
     import torch
     out = []
     cases = [(dt, r, box) for dt in ("f32", "f64") for r, box in ((1, False), (2, False), (1, True), (2, True))]
     cases += [("f32c", 1, False), ("f32c", 1, True)]
+    cases += [(dt, r, box) for dt in ("f32", "f64") for box in (False, True) for r in (3, 4)]
     for kind, r, box in cases:
         dtype = "f64" if kind == "f64" else "f32"
-        p = Problem(r, box, dtype, interior=(N3, N3, N3), accum="compensated" if kind == "f32c" else "plain")
+        steps = 100 if (box and r >= 3) else T_STEPS
+        p = Problem(r, box, dtype, interior=(N3, N3, N3), steps=steps,
+                    accum="compensated" if kind == "f32c" else "plain")
         s = time_steps(p, 1, 1)
-        g = N3 ** 3 * T_STEPS / s / 1e9
+        g = N3 ** 3 * steps / s / 1e9
         w = 4 if dtype == "f32" else 8
         out.append({"stencil": "%s3d%dr" % ("box" if box else "star", r), "dtype": kind,
                     "bt": p.info["bt"], "kernel": ("auto", "blocked", "direct")[p.info["kernel"]],
-                    "tile": [p.info["tile0"], p.info["tile1"]], "gcells": g,
+                    "tile": [p.info["tile0"], p.info["tile1"]], "steps": steps, "gcells": g,
                     "pct_hbm_bound": 100.0 * g * 2 * w / HBM_PEAK_GBS})
         print("sweep3d %s %s bt=%d: %.1f GCell/s" % (out[-1]["stencil"], kind, p.info["bt"], g),
               file=sys.stderr, flush=True)
@@ -1279,7 +1284,7 @@ def main(argv=None):
     if not args.no_sweep:
         sweep = []
         for dtype in ("f32", "f64"):
-            for r, box in STENCILS:
+            for r, box in STENCILS + [(3, True), (4, True)]:
                 p = Problem(r, box, dtype)
                 s = time_steps(p, 1, 1)
                 w = 4 if dtype == "f32" else 8
