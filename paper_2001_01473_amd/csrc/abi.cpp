@@ -92,8 +92,8 @@ int default_bt3(int kind, int box, int r, int expr) { return default_tuning3(kin
 
 // Stencils whose direct kernel measured faster than every blocked variant
 // on MI355X at 512^3: the 125-point float32 box, the compensated 27-point
-// box, and the compensated stars (row streaming: 473 vs 433 GCell/s for the
-// 7-point star, 276 vs 194 for the 13-point one).
+// box, and the compensated stars (row streaming: 501 vs 433 GCell/s for the
+// 7-point star, 309 vs 194 for the 13-point one).
 bool prefer_direct(int kind, int ndim, int box, int r) {
   if (ndim != 3) return false;
   if (!box) return kind == KIND_F32_COMP && r <= 2;

@@ -42,7 +42,7 @@ Kernel3D make3d() {
                     1,
                     kStream3DThreads / 64,
                     1,
-                    &fill_stream3d<T>,
+                    &fill_stream3d<T, R>,
                     &launch_stream3d_batch<T, ACC, R, BOX>,
                     static_cast<int>(sizeof(Stream3DArgs))};
   else

@@ -127,18 +127,20 @@ def test_row_streaming_spans_segments(s, dt):
 
 
 @pytest.mark.parametrize("kind", ["f32", "f64", "f32c"])
-@pytest.mark.parametrize("r", [1, 2, 3])
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
 def test_row_streaming_3d_spans_segments(kind, r):
     """The 3D row-streaming kernel (star stencils) on rows of several wave
-    segments (64 lanes x one 16-byte vector) plus a ragged tail, and on rows
-    shorter than one wave: the same bits as the blocked kernel at b_T = 1
-    (radius 1-2, where one is built), float64 within 1e-12 of the oracle,
-    compensated float32 bit-exact against the compensated oracle."""
+    segments (64 lanes x one 16-byte vector) plus a ragged tail, on rows
+    shorter than one wave, and on row counts that leave a wave's group of
+    2 or 4 rows partly empty (1, 3, 6, 7 rows): the same bits as the blocked
+    kernel at b_T = 1 (radius 1-2, where one is built), float64 within 1e-12
+    of the oracle, compensated float32 bit-exact against the compensated
+    oracle."""
     dt = np.float64 if kind == "f64" else np.float32
     accum = "compensated" if kind == "f32c" else "plain"
     seg = 64 * (16 // np.dtype(dt).itemsize)
     T = 2
-    for interior in ((5, 7, 2 * seg + 77), (4, 3, 19)):
+    for interior in ((5, 7, 2 * seg + 77), (4, 3, 19), (3, 1, seg + 5), (2, 6, 40)):
         case = si.make_case(97 + r, 3, r, False, interior, T)
         c_in, g_in = case.as_dtype(dt)
         say("3D row streaming", kind, "r", r, interior)
