@@ -28,7 +28,7 @@ Kernel2D make2d() {
                     0,
                     1,
                     kStreamThreads * stream2d_cpl<T>(),
-                    &fill_stream2d<T>,
+                    &fill_stream2d<T, ACC, R>,
                     &launch_stream2d_batch<T, ACC, R, BOX>,
                     static_cast<int>(sizeof(Stream2DArgs))};
 }

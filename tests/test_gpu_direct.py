@@ -104,16 +104,18 @@ def test_auto_falls_back_to_direct():
 
 
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
-@pytest.mark.parametrize("s", [(2, 1, False), (2, 2, False), (2, 1, True), (2, 2, True)], ids=_sid)
+@pytest.mark.parametrize("s", [(2, 1, False), (2, 2, False), (2, 3, False), (2, 4, False), (2, 1, True),
+                               (2, 2, True)], ids=_sid)
 def test_row_streaming_spans_segments(s, dt):
     """The row-streaming kernel on rows of several workgroup segments (512
-    threads x one 16-byte vector) plus a ragged tail, and on a row shorter
-    than one wave: the same bits as the blocked kernel at b_T = 1, and float64
-    within 1e-12 of the oracle."""
+    threads x one 16-byte vector) plus a ragged tail, on a row shorter than
+    one wave, and on row counts that leave a thread's group of 2 or 4 rows
+    partly empty (1, 3, 6, 13 rows): the same bits as the blocked kernel at
+    b_T = 1, and float64 within 1e-12 of the oracle."""
     nd, r, box = s
     seg = 512 * (16 // np.dtype(dt).itemsize)
     T = 3
-    for interior in ((13, 2 * seg + 389), (6, 37)):
+    for interior in ((13, 2 * seg + 389), (6, 37), (1, 70), (3, seg + 3)):
         case = si.make_case(91 + r, nd, r, box, interior, T)
         c_in, g_in = case.as_dtype(dt)
         say("row streaming", _sid(s), dt.__name__, interior)
