@@ -91,10 +91,18 @@ Default3D default_tuning3(int kind, int box, int r, int expr = 0) {
 int default_bt3(int kind, int box, int r, int expr) { return default_tuning3(kind, box, r, expr).bt; }
 
 // Stencils whose direct kernel measured faster than every blocked variant
-// on MI355X at 512^3: the 125-point float32 box, the compensated 27-point
-// box, and the compensated stars (row streaming: 501 vs 433 GCell/s for the
-// 7-point star, 309 vs 194 for the 13-point one).
+// on MI355X.  3D at 512^3: the 125-point float32 box, the compensated
+// 27-point box, and the compensated stars (row streaming: 501 vs 433 GCell/s
+// for the 7-point star, 309 vs 194 for the 13-point one).  2D at 16384^2:
+// the float32 81-point box (327 vs 285 at b_T = 3) and every compensated
+// stencil but the 5-point star (row streaming against the best blocked
+// depth: star r = 2..4 487 / 360 / 289 vs 450 / 294 / 229, box r = 1, 2
+// 562 / 250 vs 417 / 181; the 5-point star keeps b_T = 3, 843 vs 697).
 bool prefer_direct(int kind, int ndim, int box, int r) {
+  if (ndim == 2) {
+    if (kind == KIND_F32_COMP) return box || r >= 2;
+    return kind == KIND_F32 && box && r == 4;
+  }
   if (ndim != 3) return false;
   if (!box) return kind == KIND_F32_COMP && r <= 2;
   return (kind == KIND_F32 && r == 2) || (kind == KIND_F32_COMP && r == 1);

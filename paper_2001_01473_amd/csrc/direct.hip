@@ -7,13 +7,15 @@
 namespace s5d {
 namespace {
 
-// 2D: the row-streaming kernel (stream2d.h), except for box stencils of
-// radius 3 and 4, whose 2r+1 full-row reads per thread lose to the LDS-staged
-// tiles (measured on MI355X); 3D: the row-streaming kernel (stream3d.h) for
-// star stencils, the LDS-staged tiles for box stencils.
+// 2D: the row-streaming kernel (stream2d.h), except for float64 box
+// stencils of radius 3 and 4, whose row-streaming threads need too many
+// registers and lose to the LDS-staged tiles (measured on MI355X at 16384^2:
+// 185 vs 191 GCell/s for radius 3, 104 vs 162 for radius 4; in float32 row
+// streaming wins, 435 vs 271 and 327 vs 236); 3D: the row-streaming kernel
+// (stream3d.h) for star stencils, the LDS-staged tiles for box stencils.
 template <typename T, int ACC, int R, bool BOX>
 Kernel2D make2d() {
-  if constexpr (BOX && R >= 3)
+  if constexpr (BOX && R >= 3 && std::is_same_v<T, double>)
     return Kernel2D{&launch_direct2d<T, ACC, R, BOX>,
                     &occupancy_direct<T, ACC, 2, R, BOX>,
                     0,
