@@ -12,7 +12,10 @@ namespace {
 // registers and lose to the LDS-staged tiles (measured on MI355X at 16384^2:
 // 185 vs 191 GCell/s for radius 3, 104 vs 162 for radius 4; in float32 row
 // streaming wins, 435 vs 271 and 327 vs 236); 3D: the row-streaming kernel
-// (stream3d.h) for star stencils, the LDS-staged tiles for box stencils.
+// (stream3d.h) for star stencils and the 27-point box (at 512^3: 473 vs 235
+// GCell/s float32, 217 vs 138 float64), the LDS-staged tiles for larger boxes,
+// whose row-streaming waves hold too many rows in registers (box3d2r float32
+// 122 vs 127, float64 11 vs 70).
 template <typename T, int ACC, int R, bool BOX>
 Kernel2D make2d() {
   if constexpr (BOX && R >= 3 && std::is_same_v<T, double>)
@@ -37,14 +40,14 @@ Kernel2D make2d() {
 
 template <typename T, int ACC, int R, bool BOX>
 Kernel3D make3d() {
-  if constexpr (!BOX)
+  if constexpr (!BOX || R == 1)
     return Kernel3D{&launch_stream3d<T, ACC, R, BOX>,
                     &occupancy_stream3d<T, ACC, R, BOX>,
                     0,
                     1,
                     kStream3DThreads / 64,
                     1,
-                    &fill_stream3d<T, R>,
+                    &fill_stream3d<T, R, BOX>,
                     &launch_stream3d_batch<T, ACC, R, BOX>,
                     static_cast<int>(sizeof(Stream3DArgs))};
   else

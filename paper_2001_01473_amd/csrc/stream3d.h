@@ -1,5 +1,5 @@
-// Direct 3D kernel for star stencils: one time step per launch, streaming
-// whole rows.
+// Direct 3D kernel for star stencils and the 27-point box: one time step per
+// launch, streaming whole rows.
 //
 // Every wave64 computes one segment of 64 x CPL cells (one 16-byte vector per
 // lane) of M consecutive interior rows (plane p, rows i0 .. i0 + M - 1) of
@@ -7,13 +7,13 @@
 // plane, and workgroups run in plain dispatch order, so at any moment the
 // machine streams one window of consecutive rows and the rows a cell shares
 // with its neighbours are re-read from the caches.  For each stencil row
-// (p + d0, i + d1) a lane loads its vector straight from global memory; the
-// M + 2r rows of plane p are loaded once for all M rows, and the centre rows
-// take their r neighbours on either side from the adjacent lanes (DPP; the
-// wave's edge lanes from two wave-uniform loads).  Each cell sums its terms in
-// the canonical (d0, d1, d2) order with the same accumulation policy as the
-// blocked kernels, so the results have the same bits.  Stores are
-// non-temporal.  No LDS, no barrier: waves are independent.
+// (p + d0, i + d1) a lane loads its vector straight from global memory, once
+// for all the wave's rows that use it.  The centre rows of a star take their
+// r neighbours on either side from the adjacent lanes (DPP; the wave's edge
+// lanes from two wave-uniform loads); box rows load them per lane.  Each cell
+// sums its terms in the canonical (d0, d1, d2) order with the same
+// accumulation policy as the blocked kernels, so the results have the same
+// bits.  Stores are non-temporal.  No LDS, no barrier: waves are independent.
 #pragma once
 
 #include "kcommon.h"
@@ -33,21 +33,24 @@ struct Stream3DArgs {
 constexpr int kStream3DThreads = 512;
 
 // Rows per wave: a wave's M consecutive rows share the loads of their
-// plane's rows (M + 2r row loads instead of M (2r + 1)).  Measured at 512^3
-// against 1, 2, 3, 4 and 8 rows: 4 for radius 1 and 4, 2 for radius 2 and 3
-// (float32, float64 and compensated alike; 3 rows misalign with the
-// workgroups, 8 spill).
-template <typename T, int R>
+// planes' rows (stars: M + 2r row loads of plane p and 2r M of the other
+// planes instead of (4r + 1) M; boxes: (2r + 1)(M + 2r) instead of
+// (2r + 1)^2 M).  Measured at 512^3 against 1, 2, 3, 4 and 8 rows: for stars
+// 4 at radius 1 and 4, 2 at radius 2 and 3 (float32, float64 and compensated
+// alike; 3 rows misalign with the workgroups, 8 spill); 4 for the 27-point
+// box.
+template <typename T, int R, bool BOX>
 constexpr int stream3d_rows() {
+  if constexpr (BOX) return 4;
   return R == 2 || R == 3 ? 2 : 4;
 }
 
-template <typename T, int ACC, int R>
+template <typename T, int ACC, int R, bool BOX>
 __device__ __forceinline__ void stream3d_wave(const Stream3DArgs& a, int64_t gw) {
   constexpr int CPL = 16 / static_cast<int>(sizeof(T));
   constexpr int E = 2 * R + 1;
-  constexpr int M = stream3d_rows<T, R>();
-  constexpr bool DPPH = R <= CPL;  // a lane shift reaches one neighbouring lane only
+  constexpr int M = stream3d_rows<T, R, BOX>();
+  constexpr bool DPPH = !BOX && R <= CPL;  // a lane shift reaches one neighbouring lane only
   const int P1 = a.I1 + 2 * R, P2 = a.I2 + 2 * R;
   const int ws = static_cast<int>(gw % a.nws);
   const int64_t rg = gw / a.nws;
@@ -85,6 +88,13 @@ __device__ __forceinline__ void stream3d_wave(const Stream3DArgs& a, int64_t gw)
           x[R + CPL + J] = lane == 63 ? (rc < P2 ? rgt : T(0)) : x[R + CPL + J];
         });
       }
+    } else if (c0 + CPL + R <= P2) {
+      const LaneVec<T, CPL> v = *reinterpret_cast<const LaneVec<T, CPL>*>(rp + c0);
+      sfor<CPL>([&](auto K) S5D_INL { x[R + K] = v.v[K]; });
+      sfor<R>([&](auto J) S5D_INL {
+        x[J] = rp[c0 - R + J];
+        x[R + CPL + J] = rp[c0 + CPL + J];
+      });
     } else {
       sfor<CPL + 2 * R>([&](auto X) S5D_INL {
         const int col = c0 - R + X;
@@ -97,6 +107,27 @@ __device__ __forceinline__ void stream3d_wave(const Stream3DArgs& a, int64_t gw)
   // rows of its plane in d1 order (the centre row with its d2 terms), then
   // (d0 > 0)
   Accum<T, ACC> acc[M][CPL];
+  if constexpr (BOX) {
+    // planes p - R .. p + R, each with the rows i0 - R + Q of that plane
+    sfor<E>([&](auto D0) S5D_INL {
+      sfor<M + 2 * R>([&](auto Q) S5D_INL {
+        T x[CPL + 2 * R];
+        load_row(x, p - R + D0, i0 - R + Q, true);
+        sfor<M>([&](auto MI) S5D_INL {
+          constexpr int d1 = Q - MI - R;
+          if constexpr (d1 >= -R && d1 <= R) {
+            sfor<E>([&](auto D2) S5D_INL {
+              const T ck = c[(D0 * E + d1 + R) * E + D2];
+              sfor<CPL>([&](auto K) S5D_INL {
+                if constexpr (D0 == 0 && d1 == -R && D2 == 0) acc[MI][K].first(ck, x[K + D2]);
+                else acc[MI][K].add(ck, x[K + D2]);
+              });
+            });
+          }
+        });
+      });
+    });
+  } else {
   sfor<R>([&](auto J) S5D_INL {  // (d0, 0, 0), d0 < 0
     sfor<M>([&](auto MI) S5D_INL {
       T x[CPL + 2 * R];
@@ -131,6 +162,7 @@ __device__ __forceinline__ void stream3d_wave(const Stream3DArgs& a, int64_t gw)
       sfor<CPL>([&](auto K) S5D_INL { acc[MI][K].add(c[5 * R + 1 + J], x[R + K]); });
     });
   });
+  }
 
   sfor<M>([&](auto MI) S5D_INL {
     if (i0 + MI < a.I1 + R) {
@@ -157,9 +189,8 @@ template <typename T, int ACC, int R, bool BOX>
 __device__ __forceinline__ void stream3d_block(const Stream3DArgs& a, int lb) {
   const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
   const int64_t gw = static_cast<int64_t>(lb) * (kStream3DThreads / 64) + w;
-  static_assert(!BOX, "box stencils take the LDS-staged direct kernel");
   if (gw >= a.nwaves) return;
-  stream3d_wave<T, ACC, R>(a, gw);
+  stream3d_wave<T, ACC, R, BOX>(a, gw);
 }
 
 template <typename T, int ACC, int R, bool BOX>
@@ -175,7 +206,7 @@ __global__ __launch_bounds__(kStream3DThreads) void stream3d_batch_kernel(const 
   stream3d_block<T, ACC, R, BOX>(a, __builtin_amdgcn_readfirstlane(m.block));
 }
 
-template <typename T, int R>
+template <typename T, int R, bool BOX>
 int64_t stream3d_args(Stream3DArgs& a, const Round3D& rd) {
   constexpr int CPL = 16 / static_cast<int>(sizeof(T));
   a.src = rd.src;
@@ -185,7 +216,7 @@ int64_t stream3d_args(Stream3DArgs& a, const Round3D& rd) {
   a.I1 = rd.I1;
   a.I2 = rd.I2;
   a.nws = (rd.I2 + 64 * CPL - 1) / (64 * CPL);
-  a.ngr = (rd.I1 + stream3d_rows<T, R>() - 1) / stream3d_rows<T, R>();
+  a.ngr = (rd.I1 + stream3d_rows<T, R, BOX>() - 1) / stream3d_rows<T, R, BOX>();
   a.nwaves = static_cast<int64_t>(rd.I0) * a.ngr * a.nws;
   const int64_t nblk = (a.nwaves + kStream3DThreads / 64 - 1) / (kStream3DThreads / 64);
   return nblk > INT32_MAX ? 0 : nblk;
@@ -194,17 +225,17 @@ int64_t stream3d_args(Stream3DArgs& a, const Round3D& rd) {
 template <typename T, int ACC, int R, bool BOX>
 hipError_t launch_stream3d(const Round3D& rd) {
   Stream3DArgs a;
-  const int64_t nblk = stream3d_args<T, R>(a, rd);
+  const int64_t nblk = stream3d_args<T, R, BOX>(a, rd);
   if (nblk == 0) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((stream3d_kernel<T, ACC, R, BOX>), dim3(static_cast<unsigned>(nblk)), dim3(kStream3DThreads), 0,
                      rd.stream, a);
   return hipGetLastError();
 }
 
-template <typename T, int R>
+template <typename T, int R, bool BOX>
 int fill_stream3d(void* item, const Round3D& rd) {
   Stream3DArgs a;
-  const int64_t nblk = stream3d_args<T, R>(a, rd);
+  const int64_t nblk = stream3d_args<T, R, BOX>(a, rd);
   __builtin_memcpy(item, &a, sizeof(a));
   return static_cast<int>(nblk);
 }

@@ -129,9 +129,10 @@ def test_row_streaming_spans_segments(s, dt):
 
 
 @pytest.mark.parametrize("kind", ["f32", "f64", "f32c"])
-@pytest.mark.parametrize("r", [1, 2, 3, 4])
-def test_row_streaming_3d_spans_segments(kind, r):
-    """The 3D row-streaming kernel (star stencils) on rows of several wave
+@pytest.mark.parametrize("r,box", [(1, False), (2, False), (3, False), (4, False), (1, True)],
+                         ids=["star1", "star2", "star3", "star4", "box1"])
+def test_row_streaming_3d_spans_segments(kind, r, box):
+    """The 3D row-streaming kernel (stars, 27-point box) on rows of several wave
     segments (64 lanes x one 16-byte vector) plus a ragged tail, on rows
     shorter than one wave, and on row counts that leave a wave's group of
     2 or 4 rows partly empty (1, 3, 6, 7 rows): the same bits as the blocked
@@ -143,18 +144,18 @@ def test_row_streaming_3d_spans_segments(kind, r):
     seg = 64 * (16 // np.dtype(dt).itemsize)
     T = 2
     for interior in ((5, 7, 2 * seg + 77), (4, 3, 19), (3, 1, seg + 5), (2, 6, 40)):
-        case = si.make_case(97 + r, 3, r, False, interior, T)
+        case = si.make_case(97 + r, 3, r, box, interior, T)
         c_in, g_in = case.as_dtype(dt)
-        say("3D row streaming", kind, "r", r, interior)
-        a, ia = run_gpu(g_in, radius=r, box=False, coeffs=case.coeffs, steps=T, accum=accum, kernel="direct")
+        say("3D row streaming", kind, "r", r, "box", box, interior)
+        a, ia = run_gpu(g_in, radius=r, box=box, coeffs=case.coeffs, steps=T, accum=accum, kernel="direct")
         assert ia["kernel"] == 2
         if r <= 2:
-            b, ib = run_gpu(g_in, radius=r, box=False, coeffs=case.coeffs, steps=T, accum=accum,
+            b, ib = run_gpu(g_in, radius=r, box=box, coeffs=case.coeffs, steps=T, accum=accum,
                             kernel="blocked", bt=1)
             np.testing.assert_array_equal(a, b)
         if kind == "f64":
-            ref = oracle.sweep(g_in, radius=r, box=False, coeffs=c_in, steps=T)
+            ref = oracle.sweep(g_in, radius=r, box=box, coeffs=c_in, steps=T)
             assert max(rel_errors(a, ref)) <= 1e-12
         elif kind == "f32c":
-            want = oracle.sweep(g_in, radius=r, box=False, coeffs=c_in, steps=T, accum="compensated")
+            want = oracle.sweep(g_in, radius=r, box=box, coeffs=c_in, steps=T, accum="compensated")
             np.testing.assert_array_equal(a, want)
