@@ -743,14 +743,15 @@ def _accuracy_row(name, kind, got, ref, steps, n, max_a0, bound_kind):
             "ok": bool(ok)}
 
 
-def accuracy_full(which="all", md=None, n2=N, n3=N3, stencils2d=STENCILS):
+def accuracy_full(which="all", md=None, n2=N, n3=N3, stencils2d=STENCILS, kinds=("f64", "f32", "f32c")):
     """Whole-grid comparison with the CPU oracle at the benchmark sizes and
     T = 1000: the six 2D stencils at 16384^2 and the 7-point star and 27-point
     box at 512^3.  Float64 runs on float64 inputs against the oracle on the same
     inputs (bar: normwise and elementwise relative error <= 1e-12); float32 and
     compensated float32 on float32-rounded grid and coefficients against the
     float64 oracle run on those rounded inputs (bars: T*(gamma_n + u)*max|A0|
-    plain, T*(u + gamma_n^2)*max|A0| compensated).  Every cell is compared."""
+    plain, T*(u + gamma_n^2)*max|A0| compensated).  Every cell is compared.
+    `kinds`: the subset of f64, f32, f32c to run."""
     import torch
     import oracle
     import paper_2001_01473_amd as s5d
@@ -781,18 +782,21 @@ def accuracy_full(which="all", md=None, n2=N, n3=N3, stencils2d=STENCILS):
         n = si.n_points(ndim, r, box)
         c = si.random_coeffs(rng, n)
         grid = si.random_grid(rng, si.padded_shape(interior, r))
-        t0 = time.perf_counter()
-        ref = oracle.sweep(grid, radius=r, box=box, coeffs=c, steps=T_STEPS)
-        t_or = time.perf_counter() - t0
-        print("accuracy-full %s: float64 oracle %.0f s" % (name, t_or), file=sys.stderr, flush=True)
-        got, info = gpu_run(grid, ndim, r, box, c, "f64", "plain")
-        row = _accuracy_row(name, "f64", got, ref, T_STEPS, n, float(grid.max()), "f64")
-        row.update(bt=info["bt"], kernel=("auto", "blocked", "direct")[info["kernel"]], oracle_s=t_or)
-        rows.append(row)
-        print(json.dumps(row), flush=True)
-        del got, ref
+        if "f64" in kinds:
+            t0 = time.perf_counter()
+            ref = oracle.sweep(grid, radius=r, box=box, coeffs=c, steps=T_STEPS)
+            t_or = time.perf_counter() - t0
+            print("accuracy-full %s: float64 oracle %.0f s" % (name, t_or), file=sys.stderr, flush=True)
+            got, info = gpu_run(grid, ndim, r, box, c, "f64", "plain")
+            row = _accuracy_row(name, "f64", got, ref, T_STEPS, n, float(grid.max()), "f64")
+            row.update(bt=info["bt"], kernel=("auto", "blocked", "direct")[info["kernel"]], oracle_s=t_or)
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+            del got, ref
         g32, c32 = grid.astype(np.float32), c.astype(np.float32)
         del grid
+        if "f32" not in kinds and "f32c" not in kinds:
+            continue
         t0 = time.perf_counter()
         ref = oracle.sweep(g32.astype(np.float64), radius=r, box=box, coeffs=c32.astype(np.float64),
                            steps=T_STEPS)
@@ -800,6 +804,8 @@ def accuracy_full(which="all", md=None, n2=N, n3=N3, stencils2d=STENCILS):
         print("accuracy-full %s: float64 oracle on float32 inputs %.0f s" % (name, t_or), file=sys.stderr,
               flush=True)
         for kind, accum in (("f32", "plain"), ("f32c", "compensated")):
+            if kind not in kinds:
+                continue
             got, info = gpu_run(g32, ndim, r, box, c32.astype(np.float64), "f32", accum)
             row = _accuracy_row(name, kind, got, ref, T_STEPS, n, float(g32.max()),
                                 "plain" if accum == "plain" else "comp")
@@ -812,8 +818,8 @@ def accuracy_full(which="all", md=None, n2=N, n3=N3, stencils2d=STENCILS):
         cpu = _host_cpu()
         with open(md, "w") as f:
             f.write("# Whole-grid accuracy against the CPU oracle, T = 1000\n\n")
-            f.write("Command (from the repository root): `python bench.py --accuracy-full %s --md <this file>`\n\n"
-                    % which)
+            f.write("Command (from the repository root): `python bench.py --accuracy-full %s --acc-kinds %s "
+                    "--md <this file>`\n\n" % (which, ",".join(kinds)))
             f.write("Oracle: the naive double-buffered loop in C (no FMA), OpenMP over axis 0, %d threads on "
                     "%s.  Every cell of the GPU result is compared with the oracle's.  float64 rows: "
                     "float64 inputs, bar 1e-12 on the normwise (max|g-o|/max|o|) and elementwise "
@@ -1183,6 +1189,8 @@ def main(argv=None):
     ap.add_argument("--md", default=None, help="with --accuracy-full: write a markdown table here")
     ap.add_argument("--acc-stencils", default=None,
                     help="with --accuracy-full: comma-separated 2D stencils (e.g. star2d1r,box2d2r)")
+    ap.add_argument("--acc-kinds", default=None,
+                    help="with --accuracy-full: comma-separated subset of f64,f32,f32c")
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-loads", default="0.5,0.9")
     ap.add_argument("--serve-budgets-gib", default="64")
@@ -1237,7 +1245,8 @@ def main(argv=None):
         if args.acc_stencils:
             names = args.acc_stencils.split(",")
             sel = [(r, box) for r, box in STENCILS if stencil_name(r, box) in names]
-        rows = accuracy_full(args.accuracy_full, args.md, stencils2d=sel)
+        kinds = tuple(args.acc_kinds.split(",")) if args.acc_kinds else ("f64", "f32", "f32c")
+        rows = accuracy_full(args.accuracy_full, args.md, stencils2d=sel, kinds=kinds)
         return 0 if all(r["ok"] for r in rows) else 1
     if args.write_tuning:
         os.environ["S5D_TUNING_FILE"] = ""  # measure against the built-in defaults
