@@ -586,11 +586,13 @@ def bench_batch(reps=2):
             p.close()
         del b0, b1, init
         torch.cuda.empty_cache()
-    out["speedup_vs_sequential_f32"] = (out["batched_graph_f32_gcells"] /
-                                        out["sequential_f32_gcells"])
-    out["persistent_speedup_vs_sequential_f32"] = (out["persistent_graph_f32_gcells"] /
-                                                   out["sequential_f32_gcells"])
-    out["persistent_vs_plain_f64"] = out["persistent_graph_f32_gcells"] / out["sequential_sync_f64_gcells"]
+    # against the faster of the two one-grid-at-a-time modes
+    seq32 = max(out["sequential_f32_gcells"], out["sequential_sync_f32_gcells"])
+    seq64 = max(out["sequential_f64_gcells"], out["sequential_sync_f64_gcells"])
+    out["speedup_vs_sequential_f32"] = out["batched_graph_f32_gcells"] / seq32
+    out["persistent_speedup_vs_sequential_f32"] = out["persistent_graph_f32_gcells"] / seq32
+    out["batched_vs_plain_f64"] = out["batched_graph_f32_gcells"] / seq64
+    out["persistent_vs_plain_f64"] = out["persistent_graph_f32_gcells"] / seq64
     return out
 
 
