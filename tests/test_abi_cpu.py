@@ -262,3 +262,29 @@ def test_run_fields_validation():
 def test_waves_per_eu_is_reserved():
     st, _ = _create(tuning=_lib.make_tuning(waves_per_eu=2))
     assert st == _lib.S5D_EINVAL
+
+
+@pytest.mark.parametrize("ndim,radius,box,dtype,accum,want", [
+    (2, 1, False, _lib.F32, 1, "blocked"),   # compensated 5-point star: b_T = 3
+    (2, 2, False, _lib.F32, 1, "direct"),    # other compensated 2D stencils: one step
+    (2, 1, True, _lib.F32, 1, "direct"),
+    (2, 4, True, _lib.F32, 0, "direct"),     # float32 81-point box
+    (2, 4, True, _lib.F64, 0, "blocked"),    # float64 81-point box: blocked b_T = 1
+    (2, 1, False, _lib.F32, 0, "blocked"),
+    (3, 1, True, _lib.F32, 1, "direct"),     # compensated 27-point box
+    (3, 1, False, _lib.F32, 0, "blocked"),
+])
+def test_default_kernel_choice(ndim, radius, box, dtype, accum, want):
+    """Which kernel family a plan without tuning takes.  A direct plan uploads
+    its coefficients at creation, so without a GPU it ends in S5D_EDEVICE
+    where a blocked plan succeeds; with a GPU the chosen family is queried."""
+    lib = _lib.load()
+    interior = (64, 64) if ndim == 2 else (16, 16, 16)
+    st, h = _create(ndim=ndim, radius=radius, box=box, dtype=dtype, accum=accum, interior=interior)
+    if st == _lib.S5D_OK:
+        t = _lib.make_tuning()
+        assert lib.s5d_plan_query(h, ctypes.byref(t), None) == _lib.S5D_OK
+        lib.s5d_plan_destroy(h)
+        assert t.kernel == _lib.KERNELS[want]
+    else:
+        assert want == "direct" and st == _lib.S5D_EDEVICE, _lib.last_error()
