@@ -663,14 +663,14 @@ s5d_status s5d_plan_create(const s5d_desc* desc, const s5d_tuning* tuning, s5d_p
   }
   const bool no_blocking = req.bt <= 1 && req.cells_per_lane == 0 && req.rows_per_wave == 0 && req.tile0 == 0 &&
                            req.tile1 == 0 && req.stream_chunk == 0;
-  // b_T = 1 asked for: the row-streaming direct kernel (plain accumulation;
-  // 2D stars and boxes of radius <= 2, the 3D 7-point star and 27-point box)
-  // is faster than the blocked kernel at depth 1
+  // b_T = 1 asked for: the row-streaming direct kernel (2D stars and boxes of
+  // radius <= 2, the 3D 7-point star and 27-point box; plain or compensated
+  // accumulation) is faster than the blocked kernel at depth 1 (compensated
+  // at 16384^2: star2d1r 697 vs 539 GCell/s, box2d1r 562 vs 389)
   const bool linear = d.expr == S5D_EXPR_LINEAR;
   if (!linear && req.kernel == S5D_KERNEL_DIRECT)
     return fail(S5D_EUNSUPPORTED, "expression stencils run on the blocked kernels only");
   const bool stream_bt1 = linear && req.kernel == S5D_KERNEL_AUTO && no_blocking && req.bt == 1 &&
-                          p->kind != KIND_F32_COMP &&
                           ((d.ndim == 2 && (!box || r <= 2)) || (d.ndim == 3 && r == 1));
   if (st != S5D_OK) {
     if (req.kernel == S5D_KERNEL_DIRECT || stream_bt1 ||
