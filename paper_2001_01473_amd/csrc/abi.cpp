@@ -94,15 +94,12 @@ int default_bt3(int kind, int box, int r, int expr) { return default_tuning3(kin
 // on MI355X.  3D at 512^3: the 125-point float32 box, the compensated
 // 27-point box, and the compensated stars (row streaming: 501 vs 433 GCell/s
 // for the 7-point star, 309 vs 194 for the 13-point one).  2D at 16384^2:
-// the float32 81-point box (327 vs 285 at b_T = 3) and every compensated
-// stencil but the 5-point star (row streaming against the best blocked
-// depth: star r = 2..4 487 / 360 / 289 vs 450 / 294 / 229, box r = 1, 2
-// 562 / 250 vs 417 / 181; the 5-point star keeps b_T = 3, 843 vs 697).
+// every compensated stencil but the 5-point star (row streaming against the
+// best blocked depth: star r = 2..4 487 / 360 / 289 vs 450 / 294 / 229,
+// box r = 1, 2 562 / 250 vs 417 / 181; the 5-point star keeps b_T = 3, 843
+// vs 697).
 bool prefer_direct(int kind, int ndim, int box, int r) {
-  if (ndim == 2) {
-    if (kind == KIND_F32_COMP) return box || r >= 2;
-    return kind == KIND_F32 && box && r == 4;
-  }
+  if (ndim == 2) return kind == KIND_F32_COMP && (box || r >= 2);
   if (ndim != 3) return false;
   if (!box) return kind == KIND_F32_COMP && r <= 2;
   return (kind == KIND_F32 && r == 2) || (kind == KIND_F32_COMP && r == 1);
@@ -161,7 +158,7 @@ Default2D default_tuning(int kind, int box, int r, int expr = 0) {
     return {r == 1 ? 8 : 5, c};
   }
   static const Default2D f32_star[4] = {{10, 4}, {7, 4}, {5, 4}, {3, 4}};
-  static const Default2D f32_box[4] = {{7, 4}, {3, 4}, {2, 4}, {2, 4}};
+  static const Default2D f32_box[4] = {{7, 4}, {3, 4}, {2, 4}, {1, 4}};
   static const Default2D f64_star[4] = {{10, 2}, {6, 2}, {3, 4}, {2, 4}};
   static const Default2D f64_box[4] = {{9, 2}, {4, 2}, {2, 4}, {2, 4}};
   static const Default2D comp_star[4] = {{3, 4}, {3, 4}, {1, 4}, {1, 4}};

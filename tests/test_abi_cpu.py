@@ -268,7 +268,7 @@ def test_waves_per_eu_is_reserved():
     (2, 1, False, _lib.F32, 1, "blocked"),   # compensated 5-point star: b_T = 3
     (2, 2, False, _lib.F32, 1, "direct"),    # other compensated 2D stencils: one step
     (2, 1, True, _lib.F32, 1, "direct"),
-    (2, 4, True, _lib.F32, 0, "direct"),     # float32 81-point box
+    (2, 4, True, _lib.F32, 0, "blocked"),    # float32 81-point box: blocked b_T = 1
     (2, 4, True, _lib.F64, 0, "blocked"),    # float64 81-point box: blocked b_T = 1
     (2, 1, False, _lib.F32, 0, "blocked"),
     (3, 1, True, _lib.F32, 1, "direct"),     # compensated 27-point box
